@@ -1,0 +1,193 @@
+/* tg.h -- C ABI of the MI355X latent Gaussian rasterizer.
+ *
+ * The operation is the neural rasterizer R_G of Tele-Aloha (arXiv 2405.14866,
+ * §4.2, "Latent-based Gaussian Splatting"): every foreground source pixel is
+ * lifted to a Gaussian with position x, latent feature f (d = C channels),
+ * scale s (3 values) and opacity alpha, and the set is splatted into the
+ * target camera Pi_novel to give the latent map F_novel = R_G({G}, Pi_novel).
+ * §4.2 makes R_G differentiable (the decoder is trained through it); §5.3
+ * runs the system under CUDA Graphs, which the serving calls mirror with HIP
+ * graphs.  The paper fixes the Gaussian rotation to identity; this ABI takes
+ * a quaternion per Gaussian, identity (1, 0, 0, 0) being the paper's case.
+ *
+ * Conventions (the paper only cites the 3D Gaussian splatting rasterizer):
+ *   - EWA projection with the perspective Jacobian, 0.3 px^2 added to the
+ *     diagonal of the 2D covariance, radius r = ceil(3 sqrt(lambda_max)),
+ *     16x16 tiles, the tile rectangle [floor((u-r)/16), floor((u+r)/16)]
+ *     (clamped to the image) is a Gaussian's support;
+ *   - per tile, Gaussians in ascending (view depth t_z, index) order;
+ *   - alpha = min(0.99, o exp(-d^T Sigma'^-1 d / 2)) at pixel centres
+ *     (i + 0.5, j + 0.5); alpha < 1/255 is skipped; a Gaussian that would take
+ *     the transmittance below 1e-4 is not blended and ends the pixel;
+ *   - F = sum_i alpha_i T_i f_i + T_final bg, alpha_out = 1 - T_final.
+ *   Culling, tile rectangles and depth keys come from a fixed float32
+ *   operation sequence, so the tile lists are reproducible bit for bit.
+ *
+ * Memory: every pointer argument is a DEVICE pointer unless marked (host).
+ * The caller owns all inputs, outputs and gradient buffers; the library
+ * owns contexts, frames and servers and the workspaces inside them.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the legacy
+ * default stream).  Every enqueue call only enqueues work on `stream` and
+ * returns; results are valid once the stream has reached that point.  No
+ * enqueue call synchronises the host or allocates memory, so a sequence of
+ * them can be captured into a HIP graph.
+ * Errors: functions return tg_status; nothing throws across the ABI.
+ * Argument errors are detected before anything is enqueued.  Overflow of
+ * the frame's key capacity is detected on the device: the frame is marked,
+ * the later kernels of that frame do nothing, and tg_frame_check reports
+ * TG_ERR_CAPACITY (the outputs of such a frame are undefined).
+ */
+#ifndef TG_H
+#define TG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tg_status {
+  TG_OK = 0,
+  TG_PENDING = 1,          /* serving: request not finished yet */
+  TG_ERR_INVALID = -1,     /* bad argument (null pointer, size, channel count) */
+  TG_ERR_OOM = -2,         /* device allocation failed (create calls only) */
+  TG_ERR_CAPACITY = -3,    /* more (tile, Gaussian) keys than the frame holds */
+  TG_ERR_BUDGET = -4,      /* serving: request larger than the memory budget */
+  TG_ERR_HIP = -5,         /* a HIP runtime call failed */
+  TG_ERR_UNSUPPORTED = -6, /* e.g. channel count not compiled in */
+  TG_ERR_NOT_FOUND = -7    /* serving: unknown ticket */
+} tg_status;
+
+/* Target camera Pi_novel (§4.2).  World -> camera x_c = R x_w + t with R
+ * row-major, OpenCV axes (x right, y down, z forward).  Pixel (i, j) has its
+ * centre at (i + 0.5, j + 0.5); u = fx x_c / z_c + cx.  Gaussians with view
+ * depth z_c <= znear are culled.  Passed by host pointer. */
+typedef struct tg_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float znear;
+} tg_camera;
+
+/* The Gaussian set {G} (§4.2: position x, latent feature f, scale s,
+ * opacity alpha), structure-of-arrays float32 in device memory:
+ *   mean    [3][n]   world position
+ *   scale   [3][n]   activated scales (> 0)
+ *   quat    [4][n]   rotation (w, x, y, z), need not be normalised, |q| > 0
+ *   opacity [n]      activated opacity in [0, 1]
+ *   feat    [n][c]   latent features, row-major
+ * c must be 8, 16, 32 or 64.  The struct itself is a host object. */
+typedef struct tg_gaussians {
+  const float* mean;
+  const float* scale;
+  const float* quat;
+  const float* opacity;
+  const float* feat;
+  int64_t n;
+  int32_t c;
+} tg_gaussians;
+
+/* Gradients with respect to the raw parameters (same layouts as the
+ * inputs): mean [3][n], log-scale [3][n] (scale = exp(log_scale)),
+ * unnormalised quaternion [4][n], opacity logit [n] (opacity =
+ * sigmoid(logit)), features [n][c].  Buffers are overwritten.  Host struct
+ * of device pointers. */
+typedef struct tg_grads {
+  float* d_mean;
+  float* d_log_scale;
+  float* d_quat;
+  float* d_opacity_logit;
+  float* d_feat;
+} tg_grads;
+
+typedef struct tg_ctx tg_ctx;
+typedef struct tg_frame tg_frame;
+typedef struct tg_server tg_server;
+
+/* Human-readable name of a status code (static string). */
+const char* tg_status_string(tg_status s);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+tg_status tg_ctx_create(int device, tg_ctx** out);
+void tg_ctx_destroy(tg_ctx* ctx);
+
+/* A frame is the resident workspace of one render: projected 2D state for
+ * up to max_n Gaussians, tile counters, up to max_keys (tile, Gaussian)
+ * keys, and the per-pixel final transmittance and last-contributor index of
+ * up to max_w x max_h pixels that the backward pass reads.  It is reused
+ * across renders; one frame serves one stream at a time.  Allocates device
+ * memory (TG_ERR_OOM on failure). */
+tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max_h,
+                          int64_t max_keys, tg_frame** out);
+void tg_frame_destroy(tg_frame* frame);
+
+/* Step 1 -- projection (§4.2 "rasterized to the targeted novel views given
+ * their projection matrix Pi_novel").  Per Gaussian: camera transform,
+ * EWA 2D covariance with dilation, conic, 3-sigma radius, tile rectangle,
+ * depth key, cull.  Reads g (n <= max_n), writes the frame's 2D state.
+ * cam is a host pointer; its width/height must fit the frame. */
+tg_status tg_project(tg_frame* frame, const tg_gaussians* g, const tg_camera* cam, void* stream);
+
+/* Step 2 -- binning: count (tile, Gaussian) keys per tile, scan, scatter the
+ * keys into per-tile segments and sort each segment by (depth key, index)
+ * with an LDS radix sort.  Uses the state of the last tg_project. */
+tg_status tg_bin_sort(tg_frame* frame, void* stream);
+
+/* Step 3 -- front-to-back blend (F_novel of §4.2).  out_feat [c][H][W]
+ * (planar float32), out_alpha [H][W]; bg [c] or NULL (black).  g must be
+ * the set given to tg_project. */
+tg_status tg_render_fwd(tg_frame* frame, const tg_gaussians* g, const float* bg, float* out_feat,
+                        float* out_alpha, void* stream);
+
+/* tg_render_fwd that also counts the blend's work: the (pixel, Gaussian)
+ * pairs each pixel evaluates before it ends and the pairs it blends.  Same
+ * results as tg_render_fwd; slower; meant for measurement.  Read the counts
+ * with tg_frame_work. */
+tg_status tg_render_fwd_counted(tg_frame* frame, const tg_gaussians* g, const float* bg,
+                                float* out_feat, float* out_alpha, void* stream);
+
+/* SYNCHRONISES the frame's last stream and writes the first n_counts (<= 5)
+ * counts of the last tg_render_fwd_counted to counts (host): the (pixel,
+ * Gaussian) pairs the per-pixel walks visit up to and including the one
+ * that ends them, the pairs blended, and three wave-level counts of the
+ * implementation (Gaussian steps a wave takes after culling, steps in
+ * which some lane passes the opacity threshold, steps in which some lane
+ * blends). */
+tg_status tg_frame_work(tg_frame* frame, int64_t* counts, int32_t n_counts);
+
+/* Adjoint of steps 1-3 (§4.2: R_G is differentiable and the decoder is
+ * trained through it).  d_feat [c][H][W], d_alpha [H][W] or NULL.  Uses the
+ * final transmittance and last-contributor index stored by the last
+ * tg_render_fwd of this frame and recomputes every earlier transmittance by
+ * walking each pixel's list backwards.  Writes the raw-parameter gradients
+ * of `out` (overwritten, device pointers; any of them may be NULL except
+ * d_feat). */
+tg_status tg_render_bwd(tg_frame* frame, const tg_gaussians* g, const float* bg,
+                        const float* d_feat, const float* d_alpha, const tg_grads* out,
+                        void* stream);
+
+/* SYNCHRONISES the frame's last stream.  Returns TG_ERR_CAPACITY when the
+ * last binning overflowed max_keys, else TG_OK; *n_keys (host, may be NULL)
+ * receives the number of keys the last binning needed. */
+tg_status tg_frame_check(tg_frame* frame, int64_t* n_keys);
+
+/* Copies of the last binning into caller buffers (device, enqueued on
+ * `stream`): tile_start [n_tiles + 1] int32 offsets into sorted [n_keys]
+ * int32 Gaussian indices, n_tiles = ceil(W/16) * ceil(H/16) of the last
+ * tg_project, n_keys from tg_frame_check; per tile the segment is ordered
+ * by (depth key, index).  Either output may be NULL. */
+tg_status tg_frame_lists(tg_frame* frame, int32_t* tile_start, int32_t* sorted, int64_t n_keys,
+                         void* stream);
+
+/* Copies of the per-pixel state of the last forward into caller buffers
+ * (device, enqueued on `stream`): T_final [H][W] float32 and last [H][W]
+ * int32 (position in the pixel's tile list of the last blended Gaussian,
+ * -1 if none).  Either output may be NULL. */
+tg_status tg_frame_pixel_state(tg_frame* frame, float* T_final, int32_t* last, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TG_H */

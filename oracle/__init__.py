@@ -46,6 +46,8 @@ def _load():
     lib.tgo_pixel_variants.restype = ct.c_int
     lib.tgo_pixel_variants.argtypes = [P, ct.c_int, ct.c_int, P, P]
     lib.tgo_render_brute.argtypes = [P, P, P, P]
+    lib.tgo_pixel_walk.restype = ct.c_int
+    lib.tgo_pixel_walk.argtypes = [P, ct.c_int, ct.c_int, P, ct.c_int]
     lib.tgo_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.tgo_fd.argtypes = [P, P, P, P, ct.c_int64, P, ct.c_double, P, P]
     _lib = lib
@@ -159,6 +161,13 @@ class Oracle:
         if nv < 0:
             return None
         return out[:nv].copy()
+
+    def pixel_walk(self, px: int, py: int) -> np.ndarray:
+        """Indices of the Gaussians a pixel's walk evaluates, in order."""
+        cap = 1 << 16
+        out = np.empty(cap, np.int32)
+        n = _load().tgo_pixel_walk(self._h, int(px), int(py), _p(out), cap)
+        return out[:min(n, cap)].copy()
 
     def render_brute(self, bg=None):
         bg = self.bg if bg is None else _f64(bg)

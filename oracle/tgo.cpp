@@ -673,6 +673,23 @@ int tgo_pixel_variants(void* h, int px, int py, const double* bg, double* out) {
   return nv;
 }
 
+// Gaussian indices a pixel's walk evaluates (up to and including the one
+// that stops it).  Returns the count (<= cap entries are written).
+int tgo_pixel_walk(void* h, int px, int py, int32_t* out, int cap) {
+  Ctx& k = *static_cast<Ctx*>(h);
+  const int64_t t = tile_of(k, px, py);
+  const int64_t s = k.tile_start[t], len = k.tile_start[t + 1] - s;
+  std::vector<double> F(k.c, 0.0);
+  std::vector<uint8_t> dec;
+  PixelRun run;
+  BlendOpts op;
+  op.dec = &dec;
+  blend_pixel(k, k.proj.data(), k.list.data() + s, len, px + 0.5, py + 0.5, F.data(), run, op);
+  const int cnt = (int)dec.size();
+  for (int i = 0; i < cnt && i < cap; ++i) out[i] = k.list[s + i];
+  return cnt;
+}
+
 // Brute force O(pixels x n): for every pixel, every Gaussian is tested for
 // "its rectangle holds this pixel's tile", the candidates are sorted by
 // (depth key, index) and blended.  Independent of the tile lists.

@@ -1,0 +1,175 @@
+"""ctypes binding of libtg.so (include/tg.h).  Argument marshalling only.
+
+Every function here has the name and argument order of its C counterpart.
+The library must have been built (``python -m paper_2405_14866_amd.build``
+or ``__graft_entry__.build()``); there is no fallback: importing this
+module without the library raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtg.so")
+
+TG_OK = 0
+TG_PENDING = 1
+TG_ERR_INVALID = -1
+TG_ERR_OOM = -2
+TG_ERR_CAPACITY = -3
+TG_ERR_BUDGET = -4
+TG_ERR_HIP = -5
+TG_ERR_UNSUPPORTED = -6
+TG_ERR_NOT_FOUND = -7
+
+# every symbol include/tg.h declares
+EXPORTS = [
+    "tg_status_string", "tg_ctx_create", "tg_ctx_destroy", "tg_frame_create",
+    "tg_frame_destroy", "tg_project", "tg_bin_sort", "tg_render_fwd", "tg_render_bwd",
+    "tg_frame_check", "tg_frame_lists", "tg_frame_pixel_state", "tg_render_fwd_counted",
+    "tg_frame_work",
+]
+
+
+class tg_camera(ct.Structure):
+    _fields_ = [("R", ct.c_float * 9), ("t", ct.c_float * 3), ("fx", ct.c_float),
+                ("fy", ct.c_float), ("cx", ct.c_float), ("cy", ct.c_float),
+                ("width", ct.c_int32), ("height", ct.c_int32), ("znear", ct.c_float)]
+
+
+class tg_gaussians(ct.Structure):
+    _fields_ = [("mean", ct.c_void_p), ("scale", ct.c_void_p), ("quat", ct.c_void_p),
+                ("opacity", ct.c_void_p), ("feat", ct.c_void_p), ("n", ct.c_int64),
+                ("c", ct.c_int32)]
+
+
+class tg_grads(ct.Structure):
+    _fields_ = [("d_mean", ct.c_void_p), ("d_log_scale", ct.c_void_p),
+                ("d_quat", ct.c_void_p), ("d_opacity_logit", ct.c_void_p),
+                ("d_feat", ct.c_void_p)]
+
+
+class TgError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libtg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2405_14866_amd.build` (hipcc, gfx950)")
+    L = ct.CDLL(LIB_PATH)
+    P, I, I64, I32 = ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int32
+    L.tg_status_string.restype = ct.c_char_p
+    L.tg_status_string.argtypes = [I]
+    L.tg_ctx_create.restype = I
+    L.tg_ctx_create.argtypes = [I, ct.POINTER(P)]
+    L.tg_ctx_destroy.argtypes = [P]
+    L.tg_frame_create.restype = I
+    L.tg_frame_create.argtypes = [P, I64, I32, I32, I64, ct.POINTER(P)]
+    L.tg_frame_destroy.argtypes = [P]
+    L.tg_project.restype = I
+    L.tg_project.argtypes = [P, ct.POINTER(tg_gaussians), ct.POINTER(tg_camera), P]
+    L.tg_bin_sort.restype = I
+    L.tg_bin_sort.argtypes = [P, P]
+    L.tg_render_fwd.restype = I
+    L.tg_render_fwd.argtypes = [P, ct.POINTER(tg_gaussians), P, P, P, P]
+    L.tg_render_fwd_counted.restype = I
+    L.tg_render_fwd_counted.argtypes = [P, ct.POINTER(tg_gaussians), P, P, P, P]
+    L.tg_frame_work.restype = I
+    L.tg_frame_work.argtypes = [P, ct.POINTER(I64), I32]
+    L.tg_render_bwd.restype = I
+    L.tg_render_bwd.argtypes = [P, ct.POINTER(tg_gaussians), P, P, P, ct.POINTER(tg_grads), P]
+    L.tg_frame_check.restype = I
+    L.tg_frame_check.argtypes = [P, ct.POINTER(I64)]
+    L.tg_frame_lists.restype = I
+    L.tg_frame_lists.argtypes = [P, P, P, I64, P]
+    L.tg_frame_pixel_state.restype = I
+    L.tg_frame_pixel_state.argtypes = [P, P, P, P]
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    return lib().tg_status_string(int(s)).decode()
+
+
+def check(status: int, what: str) -> int:
+    if status not in (TG_OK, TG_PENDING):
+        raise TgError(status, what)
+    return status
+
+
+# ------------------------------------------------------------ thin wrappers
+def tg_ctx_create(device: int) -> int:
+    out = ct.c_void_p()
+    check(lib().tg_ctx_create(int(device), ct.byref(out)), "tg_ctx_create")
+    return out.value
+
+
+def tg_ctx_destroy(ctx: int) -> None:
+    lib().tg_ctx_destroy(ctx)
+
+
+def tg_frame_create(ctx: int, max_n: int, max_w: int, max_h: int, max_keys: int) -> int:
+    out = ct.c_void_p()
+    check(lib().tg_frame_create(ctx, int(max_n), int(max_w), int(max_h), int(max_keys),
+                                ct.byref(out)), "tg_frame_create")
+    return out.value
+
+
+def tg_frame_destroy(frame: int) -> None:
+    lib().tg_frame_destroy(frame)
+
+
+def tg_project(frame: int, g: tg_gaussians, cam: tg_camera, stream: int) -> int:
+    return lib().tg_project(frame, ct.byref(g), ct.byref(cam), stream)
+
+
+def tg_bin_sort(frame: int, stream: int) -> int:
+    return lib().tg_bin_sort(frame, stream)
+
+
+def tg_render_fwd(frame: int, g: tg_gaussians, bg: int, out_feat: int, out_alpha: int,
+                  stream: int) -> int:
+    return lib().tg_render_fwd(frame, ct.byref(g), bg, out_feat, out_alpha, stream)
+
+
+def tg_render_fwd_counted(frame: int, g: tg_gaussians, bg: int, out_feat: int, out_alpha: int,
+                          stream: int) -> int:
+    return lib().tg_render_fwd_counted(frame, ct.byref(g), bg, out_feat, out_alpha, stream)
+
+
+def tg_frame_work(frame: int, n_counts: int = 5):
+    """(n_eval, n_blend, wave_steps, wave_pass, wave_blend)[:n_counts]"""
+    arr = (ct.c_int64 * 5)()
+    check(lib().tg_frame_work(frame, arr, int(n_counts)), "tg_frame_work")
+    return tuple(int(x) for x in arr[:n_counts])
+
+
+def tg_render_bwd(frame: int, g: tg_gaussians, bg: int, d_feat: int, d_alpha: int,
+                  grads: tg_grads, stream: int) -> int:
+    return lib().tg_render_bwd(frame, ct.byref(g), bg, d_feat, d_alpha, ct.byref(grads), stream)
+
+
+def tg_frame_check(frame: int):
+    n = ct.c_int64(0)
+    st = lib().tg_frame_check(frame, ct.byref(n))
+    return st, int(n.value)
+
+
+def tg_frame_lists(frame: int, tile_start: int, sorted_: int, n_keys: int, stream: int) -> int:
+    return lib().tg_frame_lists(frame, tile_start, sorted_, int(n_keys), stream)
+
+
+def tg_frame_pixel_state(frame: int, T_final: int, last: int, stream: int) -> int:
+    return lib().tg_frame_pixel_state(frame, T_final, last, stream)

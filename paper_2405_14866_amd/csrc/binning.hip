@@ -1,0 +1,353 @@
+// binning.hip -- step 2 of the rasterizer: (tile, Gaussian) keys grouped by
+// tile and sorted by (view depth, index) inside each tile (gfx950).
+//
+// The order the blend needs is ascending (tile, depth key, Gaussian index).
+// It is produced as a most-significant-digit split on the tile followed by
+// an LDS radix sort of each tile's segment:
+//
+//   k_count  per workgroup of 1024 Gaussians, count keys per tile in LDS
+//            (ds_add), then one global atomic per (workgroup, touched tile);
+//   k_scan   one workgroup: exclusive scan of the tile counts -> segment
+//            offsets; the key total is checked against the frame capacity
+//            on the device (no host round trip);
+//   k_fill   same LDS binning, then one global atomic per (workgroup, tile)
+//            reserves a contiguous run of the tile's segment and LDS
+//            atomics hand out slots inside it; each slot receives the 64-bit
+//            key (depth << 32) | index.  The order inside a segment is not
+//            deterministic here; the sort makes it so;
+//   k_sort   one 256-lane workgroup per tile: the segment is loaded into LDS
+//            and sorted by a stable least-significant-digit radix sort with
+//            8-bit digits (ranking within each wave64 by ballot matching,
+//            digit offsets by a wave-level scan, four barriers per pass) on
+//            the depth bits alone, re-based to the segment's minimum (about
+//            three passes); only a segment that holds two equal depths is
+//            sorted again on the composite (depth - min, index - min) key.
+//            Either way the result is the unique (depth, index) order.
+//            Segments up to 2048 keys run in a 32 KB-LDS launch (four
+//            workgroups per CU), larger ones in a second launch with 128 KB,
+//            and beyond 8192 keys on global scratch buffers.
+//
+// Compared with a global LSD sort of all K keys (4-6 passes of K x 12-24 B
+// over HBM plus a launch per pass), the keys cross HBM about three times.
+#include "tg_internal.h"
+
+namespace tg {
+namespace {
+
+__device__ __forceinline__ void rect_of(uint2 r, int& x0, int& x1, int& y0, int& y1) {
+  x0 = (int)(r.x & 0xffffu); x1 = (int)(r.x >> 16);
+  y0 = (int)(r.y & 0xffffu); y1 = (int)(r.y >> 16);
+}
+
+template <bool LDS_BINS>
+__global__ void __launch_bounds__(1024) k_count(BinArgs a) {
+  extern __shared__ int32_t bins[];
+  const int tid = threadIdx.x;
+  if (LDS_BINS) {
+    for (int t = tid; t < a.n_tiles; t += 1024) bins[t] = 0;
+    __syncthreads();
+  }
+  const int64_t g0 = (int64_t)blockIdx.x * BIN_CHUNK;
+  const int64_t g1 = min(a.n, g0 + BIN_CHUNK);
+  for (int64_t g = g0 + tid; g < g1; g += 1024) {
+    int x0, x1, y0, y1;
+    rect_of(a.rect[g], x0, x1, y0, y1);
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) {
+        const int t = ty * a.tiles_x + tx;
+        if (LDS_BINS) atomicAdd(&bins[t], 1);
+        else atomicAdd(&a.tile_count[t], 1);
+      }
+  }
+  if (LDS_BINS) {
+    __syncthreads();
+    for (int t = tid; t < a.n_tiles; t += 1024) {
+      const int v = bins[t];
+      if (v) atomicAdd(&a.tile_count[t], v);
+    }
+  }
+}
+
+// exclusive scan of tile counts (one workgroup of 1024 lanes)
+__global__ void __launch_bounds__(1024) k_scan(BinArgs a) {
+  __shared__ int64_t part[1024];
+  const int tid = threadIdx.x;
+  const int per = (a.n_tiles + 1023) / 1024;
+  const int b = min(a.n_tiles, tid * per), e = min(a.n_tiles, b + per);
+  int64_t sum = 0;
+  for (int t = b; t < e; ++t) sum += a.tile_count[t];
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // Hillis-Steele inclusive scan
+    const int64_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = part[tid] - sum;
+  const int64_t total = part[1023];
+  const bool over = total > a.key_cap;
+  for (int t = b; t < e; ++t) {
+    const int32_t v = over ? 0 : (int32_t)run;
+    a.tile_start[t] = v;
+    a.tile_cursor[t] = v;
+    run += a.tile_count[t];
+  }
+  if (tid == 1023) {
+    a.tile_start[a.n_tiles] = over ? 0 : (int32_t)total;
+    a.dev->n_keys = total;
+    a.dev->overflow = over ? 1 : 0;
+  }
+}
+
+template <bool LDS_BINS>
+__global__ void __launch_bounds__(1024) k_fill(BinArgs a) {
+  if (a.dev->overflow) return;
+  extern __shared__ int32_t bins[];
+  const int tid = threadIdx.x;
+  const int64_t g0 = (int64_t)blockIdx.x * BIN_CHUNK;
+  const int64_t g1 = min(a.n, g0 + BIN_CHUNK);
+  if (LDS_BINS) {
+    for (int t = tid; t < a.n_tiles; t += 1024) bins[t] = 0;
+    __syncthreads();
+    for (int64_t g = g0 + tid; g < g1; g += 1024) {
+      int x0, x1, y0, y1;
+      rect_of(a.rect[g], x0, x1, y0, y1);
+      for (int ty = y0; ty <= y1; ++ty)
+        for (int tx = x0; tx <= x1; ++tx) atomicAdd(&bins[ty * a.tiles_x + tx], 1);
+    }
+    __syncthreads();
+    // reserve this workgroup's run inside every touched tile segment
+    for (int t = tid; t < a.n_tiles; t += 1024) {
+      const int v = bins[t];
+      if (v) bins[t] = atomicAdd(&a.tile_cursor[t], v);
+    }
+    __syncthreads();
+  }
+  for (int64_t g = g0 + tid; g < g1; g += 1024) {
+    int x0, x1, y0, y1;
+    rect_of(a.rect[g], x0, x1, y0, y1);
+    if (x0 > x1) continue;
+    const uint64_t key = ((uint64_t)a.depth[g] << 32) | (uint64_t)(uint32_t)g;
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) {
+        const int t = ty * a.tiles_x + tx;
+        const int slot = LDS_BINS ? atomicAdd(&bins[t], 1) : atomicAdd(&a.tile_cursor[t], 1);
+        a.keys[slot] = key;
+      }
+  }
+}
+
+// ------------------------------------------------------------ segment sort
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// lanes of the wave whose 8-bit digit equals this lane's (valid lanes only)
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int bit_length(uint64_t x) { return x ? 64 - __clzll(x) : 0; }
+
+// Shared scratch of the segment sort.
+struct SortShared {
+  uint32_t hist[4][256];   // per-wave digit counts, then running offsets
+  uint32_t wtot[4];
+  uint64_t red[4][4];
+};
+
+// One stable pass over digit (key >> shift) & 255 of elements [0, n).
+// Wave w owns the contiguous element range [w * per, (w + 1) * per) and
+// visits it in order, 64 at a time, so elements with equal digits keep
+// their input order.  hist must be zero on entry and is zero on exit.
+template <typename Ptr>
+__device__ __forceinline__ void radix_pass(Ptr src, Ptr dst, int n, int shift, SortShared& sh) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int per = ((n + 255) / 256) * 64;
+  const int b = min(n, w * per), e = min(n, b + per);
+  for (int j0 = b; j0 < e; j0 += 64) {
+    const int j = j0 + lane;
+    const bool valid = j < e;
+    const uint32_t d = valid ? (uint32_t)(src[j] >> shift) & 255u : 0u;
+    const uint64_t peers = match_digit(d, valid);
+    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&sh.hist[w][d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  // digit-major, wave-minor exclusive offsets; wave w scans digits [64 w, 64 w + 64)
+  const int d = 64 * w + lane;
+  const uint32_t h0 = sh.hist[0][d], h1 = sh.hist[1][d], h2 = sh.hist[2][d], h3 = sh.hist[3][d];
+  const uint32_t t = h0 + h1 + h2 + h3;
+  const uint32_t incl = wave_incl_scan(t, lane);
+  if (lane == 63) sh.wtot[w] = incl;
+  __syncthreads();
+  uint32_t base = incl - t;
+  for (int q = 0; q < w; ++q) base += sh.wtot[q];
+  sh.hist[0][d] = base;
+  sh.hist[1][d] = base + h0;
+  sh.hist[2][d] = base + h0 + h1;
+  sh.hist[3][d] = base + h0 + h1 + h2;
+  __syncthreads();
+  for (int j0 = b; j0 < e; j0 += 64) {
+    const int j = j0 + lane;
+    const bool valid = j < e;
+    const uint64_t v = valid ? (uint64_t)src[j] : 0ull;
+    const uint32_t dg = (uint32_t)(v >> shift) & 255u;
+    const uint64_t peers = match_digit(dg, valid);
+    const uint32_t pos = valid ? sh.hist[w][dg] : 0u;
+    if (valid) dst[pos + (uint32_t)__popcll(peers & lanemask_lt())] = v;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (peers & lanemask_lt()) == 0) sh.hist[w][dg] = pos + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  for (int q = lane; q < 256; q += 64) sh.hist[w][q] = 0;   // wave-private row, next pass counts into it
+}
+
+// LSD passes over bits [shift0, shift0 + bits); returns the buffer holding the result.
+template <typename Ptr>
+__device__ __forceinline__ Ptr radix_sort(Ptr a, Ptr b, int n, int shift0, int bits, SortShared& sh) {
+  const int passes = (bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    radix_pass(a, b, n, shift0 + 8 * p, sh);
+    Ptr t = a; a = b; b = t;
+  }
+  return a;
+}
+
+// Segment sort of tiles whose key count lies in (lo, hi]: sort by depth
+// alone (the key's high half, re-based to its minimum) and, only if two
+// keys of the segment have the same depth, redo it on the composite
+// (depth, index) key.  Either way the result is the (depth, index) order.
+// Segments above CAP run the composite sort on the global scratch buffers.
+template <int CAP>
+__global__ void __launch_bounds__(256) k_sort(BinArgs a, int lo, int hi) {
+  if (a.dev->overflow) return;
+  const int t = blockIdx.x;
+  const int s = a.tile_start[t], e = a.tile_start[t + 1];
+  const int n = e - s;
+  if (n <= lo || n > hi) return;
+  const int tid = threadIdx.x, w = tid >> 6;
+  if (n == 1) {
+    if (tid == 0) a.sorted[s] = (int32_t)(uint32_t)a.keys[s];
+    return;
+  }
+  __shared__ uint64_t bufA[CAP];
+  __shared__ uint64_t bufB[CAP];
+  __shared__ SortShared sh;
+  for (int q = tid; q < 4 * 256; q += 256) (&sh.hist[0][0])[q] = 0;
+  // ranges of depth and index in the segment
+  uint64_t dmin = ~0ull, dmax = 0, imin = ~0ull, imax = 0;
+  for (int j = tid; j < n; j += 256) {
+    const uint64_t k = a.keys[s + j];
+    const uint64_t d = k >> 32, i = k & 0xffffffffull;
+    dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
+    imin = i < imin ? i : imin; imax = i > imax ? i : imax;
+  }
+  dmin = wave_min_u64(dmin); dmax = wave_max_u64(dmax);
+  imin = wave_min_u64(imin); imax = wave_max_u64(imax);
+  if ((tid & 63) == 0) { sh.red[w][0] = dmin; sh.red[w][1] = dmax; sh.red[w][2] = imin; sh.red[w][3] = imax; }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    dmin = sh.red[q][0] < dmin ? sh.red[q][0] : dmin; dmax = sh.red[q][1] > dmax ? sh.red[q][1] : dmax;
+    imin = sh.red[q][2] < imin ? sh.red[q][2] : imin; imax = sh.red[q][3] > imax ? sh.red[q][3] : imax;
+  }
+  const int db = bit_length(dmax - dmin), ib = bit_length(imax - imin);
+  const uint64_t imask = ib == 0 ? 0ull : (~0ull >> (64 - ib));
+  if (n <= CAP) {
+    // depth-only pass set: element = (depth - dmin) << 32 | index
+    for (int j = tid; j < n; j += 256) {
+      const uint64_t k = a.keys[s + j];
+      bufA[j] = (((k >> 32) - dmin) << 32) | (k & 0xffffffffull);
+    }
+    __syncthreads();
+    uint64_t* res = radix_sort<uint64_t*>(bufA, bufB, n, 32, db, sh);
+    int tie = 0;
+    for (int j = tid; j + 1 < n; j += 256) tie |= (res[j] >> 32) == (res[j + 1] >> 32);
+    if (__syncthreads_or(tie)) {
+      for (int j = tid; j < n; j += 256) {
+        const uint64_t k = a.keys[s + j];
+        bufA[j] = (((k >> 32) - dmin) << ib) | ((k & 0xffffffffull) - imin);
+      }
+      __syncthreads();
+      res = radix_sort<uint64_t*>(bufA, bufB, n, 0, db + ib, sh);
+      for (int j = tid; j < n; j += 256) a.sorted[s + j] = (int32_t)(imin + (res[j] & imask));
+    } else {
+      for (int j = tid; j < n; j += 256) a.sorted[s + j] = (int32_t)(uint32_t)res[j];
+    }
+  } else {
+    uint64_t* g0 = a.keys + s;
+    uint64_t* g1 = a.keys_tmp + s;
+    for (int j = tid; j < n; j += 256) g0[j] = (((g0[j] >> 32) - dmin) << ib) | ((g0[j] & 0xffffffffull) - imin);
+    __syncthreads();
+    const uint64_t* res = radix_sort<uint64_t*>(g0, g1, n, 0, db + ib, sh);
+    for (int j = tid; j < n; j += 256) a.sorted[s + j] = (int32_t)(imin + (res[j] & imask));
+  }
+}
+
+constexpr int SORT_SMALL = 2048;   // segments up to this size: 32 KB of LDS keys, 4 workgroups per CU
+constexpr int SORT_LARGE = 8192;   // larger segments: 128 KB of LDS keys, beyond it global scratch
+
+}  // namespace
+
+hipError_t launch_bin_sort(const BinArgs& a, hipStream_t s) {
+  const int64_t chunks = (a.n + BIN_CHUNK - 1) / BIN_CHUNK;
+  const int grid = (int)(chunks > 0 ? chunks : 1);
+  const bool lds = a.n_tiles <= BIN_LDS_MAX_TILES;
+  const size_t shm = lds ? (size_t)a.n_tiles * sizeof(int32_t) : 0;
+  if (lds) hipLaunchKernelGGL(k_count<true>, dim3(grid), dim3(1024), shm, s, a);
+  else hipLaunchKernelGGL(k_count<false>, dim3(grid), dim3(1024), 0, s, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (lds) hipLaunchKernelGGL(k_fill<true>, dim3(grid), dim3(1024), shm, s, a);
+  else hipLaunchKernelGGL(k_fill<false>, dim3(grid), dim3(1024), 0, s, a);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_sort<SORT_SMALL>, dim3(a.n_tiles), dim3(256), 0, s, a, 0, SORT_SMALL);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_sort<SORT_LARGE>, dim3(a.n_tiles), dim3(256), 0, s, a, SORT_SMALL, 0x7fffffff);
+  return hipGetLastError();
+}
+
+hipError_t bin_set_attributes() {
+  const int bytes = BIN_LDS_MAX_TILES * (int)sizeof(int32_t);
+  hipError_t e = hipFuncSetAttribute((const void*)k_count<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_fill<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes);
+}
+
+}  // namespace tg

@@ -1,0 +1,353 @@
+// tg_api.hip -- host side of the C ABI declared in include/tg.h.
+//
+// Contexts and frames own device workspaces allocated once at creation;
+// the enqueue calls (tg_project, tg_bin_sort, tg_render_fwd, tg_render_bwd)
+// validate their arguments on the host, then only launch kernels on the
+// caller's stream: no allocation, no host synchronisation, no memset (the
+// kernels clear what they accumulate into), so a sequence of calls can be
+// captured into a HIP graph and replayed.
+#include <new>
+
+#include "../../include/tg.h"
+#include "tg_internal.h"
+
+struct tg_ctx {
+  int device;
+};
+
+struct tg_frame {
+  tg_ctx* ctx = nullptr;
+  int device = 0;
+  int64_t max_n = 0, max_keys = 0;
+  int32_t max_w = 0, max_h = 0, max_tiles = 0;
+  double2* xy = nullptr;
+  float4* conic_o = nullptr;
+  uint2* rect = nullptr;
+  uint32_t* depth = nullptr;
+  int32_t* tile_count = nullptr;
+  int32_t* tile_start = nullptr;
+  int32_t* tile_cursor = nullptr;
+  uint64_t* keys = nullptr;
+  uint64_t* keys_tmp = nullptr;
+  int32_t* sorted = nullptr;
+  float* T_final = nullptr;
+  int32_t* last = nullptr;
+  float* g2d = nullptr;          // [6][max_n] backward accumulators
+  tg::FrameDev* dev = nullptr;
+  // state of the last projection / render
+  int64_t n = -1;
+  int32_t c = 0;
+  tg::CamArgs cam{};
+  int32_t n_tiles = 0;
+  bool binned = false, rendered = false;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace tg {
+hipError_t bin_set_attributes();
+}
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      changed = hipSetDevice(dev) == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+bool valid_c(int32_t c) { return c == 8 || c == 16 || c == 32 || c == 64; }
+
+template <class T>
+tg_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) return TG_ERR_OOM;
+  return TG_OK;
+}
+
+void free_frame(tg_frame* f) {
+  void* ptrs[] = {f->xy, f->conic_o, f->rect, f->depth, f->tile_count, f->tile_start,
+                  f->tile_cursor, f->keys, f->keys_tmp, f->sorted, f->T_final, f->last,
+                  f->g2d, f->dev};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+tg_status check_gaussians(const tg_frame* f, const tg_gaussians* g, bool need_c) {
+  if (!g || g->n < 0 || g->n > f->max_n) return TG_ERR_INVALID;
+  if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity)) return TG_ERR_INVALID;
+  if (need_c) {
+    if (!valid_c(g->c)) return TG_ERR_UNSUPPORTED;
+    if (g->n > 0 && !g->feat) return TG_ERR_INVALID;
+  }
+  return TG_OK;
+}
+
+tg::BinArgs bin_args(tg_frame* f) {
+  tg::BinArgs b;
+  b.rect = f->rect;
+  b.depth = f->depth;
+  b.n = f->n;
+  b.tiles_x = f->cam.tiles_x;
+  b.n_tiles = f->n_tiles;
+  b.tile_count = f->tile_count;
+  b.tile_start = f->tile_start;
+  b.tile_cursor = f->tile_cursor;
+  b.keys = f->keys;
+  b.keys_tmp = f->keys_tmp;
+  b.sorted = f->sorted;
+  b.key_cap = f->max_keys;
+  b.dev = f->dev;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tg_status_string(tg_status s) {
+  switch (s) {
+    case TG_OK: return "ok";
+    case TG_PENDING: return "pending";
+    case TG_ERR_INVALID: return "invalid argument";
+    case TG_ERR_OOM: return "out of device memory";
+    case TG_ERR_CAPACITY: return "key capacity of the frame exceeded";
+    case TG_ERR_BUDGET: return "request exceeds the memory budget";
+    case TG_ERR_HIP: return "HIP runtime error";
+    case TG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case TG_ERR_NOT_FOUND: return "unknown ticket";
+  }
+  return "unknown status";
+}
+
+tg_status tg_ctx_create(int device, tg_ctx** out) {
+  if (!out) return TG_ERR_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TG_ERR_INVALID;
+  DeviceGuard guard(device);
+  if (tg::bin_set_attributes() != hipSuccess) return TG_ERR_HIP;
+  tg_ctx* c = new (std::nothrow) tg_ctx;
+  if (!c) return TG_ERR_OOM;
+  c->device = device;
+  *out = c;
+  return TG_OK;
+}
+
+void tg_ctx_destroy(tg_ctx* ctx) { delete ctx; }
+
+tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max_h,
+                          int64_t max_keys, tg_frame** out) {
+  if (!ctx || !out || max_n < 0 || max_w <= 0 || max_h <= 0 || max_keys <= 0 ||
+      max_keys >= (int64_t)1 << 31 || max_n >= (int64_t)1 << 31 || max_w > 65535 * tg::TILE ||
+      max_h > 65535 * tg::TILE)
+    return TG_ERR_INVALID;
+  *out = nullptr;
+  DeviceGuard guard(ctx->device);
+  tg_frame* f = new (std::nothrow) tg_frame;
+  if (!f) return TG_ERR_OOM;
+  f->ctx = ctx;
+  f->device = ctx->device;
+  f->max_n = max_n;
+  f->max_keys = max_keys;
+  f->max_w = max_w;
+  f->max_h = max_h;
+  const int64_t tx = (max_w + tg::TILE - 1) / tg::TILE, ty = (max_h + tg::TILE - 1) / tg::TILE;
+  f->max_tiles = (int32_t)(tx * ty);
+  const size_t npix = (size_t)max_w * max_h;
+  tg_status st = TG_OK;
+  if (st == TG_OK) st = dalloc(&f->xy, max_n);
+  if (st == TG_OK) st = dalloc(&f->conic_o, max_n);
+  if (st == TG_OK) st = dalloc(&f->rect, max_n);
+  if (st == TG_OK) st = dalloc(&f->depth, max_n);
+  if (st == TG_OK) st = dalloc(&f->tile_count, f->max_tiles);
+  if (st == TG_OK) st = dalloc(&f->tile_start, (size_t)f->max_tiles + 1);
+  if (st == TG_OK) st = dalloc(&f->tile_cursor, f->max_tiles);
+  if (st == TG_OK) st = dalloc(&f->keys, max_keys);
+  if (st == TG_OK) st = dalloc(&f->keys_tmp, max_keys);
+  if (st == TG_OK) st = dalloc(&f->sorted, max_keys);
+  if (st == TG_OK) st = dalloc(&f->T_final, npix);
+  if (st == TG_OK) st = dalloc(&f->last, npix);
+  if (st == TG_OK) st = dalloc(&f->g2d, (size_t)6 * max_n);
+  if (st == TG_OK) st = dalloc(&f->dev, 1);
+  if (st == TG_OK && hipMemset(f->dev, 0, sizeof(tg::FrameDev)) != hipSuccess) st = TG_ERR_HIP;
+  if (st == TG_OK && hipMemset(f->tile_start, 0, ((size_t)f->max_tiles + 1) * sizeof(int32_t)) != hipSuccess)
+    st = TG_ERR_HIP;
+  if (st == TG_OK && hipDeviceSynchronize() != hipSuccess) st = TG_ERR_HIP;
+  if (st != TG_OK) {
+    free_frame(f);
+    delete f;
+    return st;
+  }
+  *out = f;
+  return TG_OK;
+}
+
+void tg_frame_destroy(tg_frame* f) {
+  if (!f) return;
+  DeviceGuard guard(f->device);
+  (void)hipDeviceSynchronize();
+  free_frame(f);
+  delete f;
+}
+
+tg_status tg_project(tg_frame* f, const tg_gaussians* g, const tg_camera* cam, void* stream) {
+  if (!f || !cam) return TG_ERR_INVALID;
+  tg_status st = check_gaussians(f, g, false);
+  if (st != TG_OK) return st;
+  if (cam->width <= 0 || cam->height <= 0 || cam->width > f->max_w || cam->height > f->max_h)
+    return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  tg::CamArgs c;
+  for (int i = 0; i < 9; ++i) c.R[i] = cam->R[i];
+  for (int i = 0; i < 3; ++i) c.t[i] = cam->t[i];
+  c.fx = cam->fx; c.fy = cam->fy; c.cx = cam->cx; c.cy = cam->cy; c.znear = cam->znear;
+  c.W = cam->width; c.H = cam->height;
+  c.tiles_x = (cam->width + tg::TILE - 1) / tg::TILE;
+  c.tiles_y = (cam->height + tg::TILE - 1) / tg::TILE;
+  f->cam = c;
+  f->n = g->n;
+  f->n_tiles = c.tiles_x * c.tiles_y;
+  f->binned = f->rendered = false;
+  tg::ProjectArgs a;
+  a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.opacity = g->opacity;
+  a.n = g->n;
+  a.cam = c;
+  a.xy = f->xy; a.conic_o = f->conic_o; a.rect = f->rect; a.depth = f->depth;
+  a.tile_count = f->tile_count;
+  a.n_tiles = f->n_tiles;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  f->last_stream = s;
+  return tg::launch_project(a, s) == hipSuccess ? TG_OK : TG_ERR_HIP;
+}
+
+tg_status tg_bin_sort(tg_frame* f, void* stream) {
+  if (!f || f->n < 0) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  f->last_stream = s;
+  if (tg::launch_bin_sort(bin_args(f), s) != hipSuccess) return TG_ERR_HIP;
+  f->binned = true;
+  return TG_OK;
+}
+
+static tg_status render_fwd_impl(tg_frame* f, const tg_gaussians* g, const float* bg,
+                                 float* out_feat, float* out_alpha, void* stream, bool count) {
+  if (!f || !f->binned || !out_feat) return TG_ERR_INVALID;
+  tg_status st = check_gaussians(f, g, true);
+  if (st != TG_OK) return st;
+  if (g->n != f->n) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  tg::RenderArgs a;
+  a.xy = f->xy; a.conic_o = f->conic_o; a.feat = g->feat;
+  a.tile_start = f->tile_start; a.sorted = f->sorted;
+  a.bg = bg;
+  a.out_feat = out_feat; a.out_alpha = out_alpha;
+  a.T_final = f->T_final; a.last = f->last;
+  a.W = f->cam.W; a.H = f->cam.H; a.tiles_x = f->cam.tiles_x; a.n_tiles = f->n_tiles;
+  a.dev = f->dev;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  f->last_stream = s;
+  f->c = g->c;
+  if (tg::launch_render_fwd(a, g->c, s, count) != hipSuccess) return TG_ERR_HIP;
+  f->rendered = true;
+  return TG_OK;
+}
+
+tg_status tg_render_fwd(tg_frame* f, const tg_gaussians* g, const float* bg, float* out_feat,
+                        float* out_alpha, void* stream) {
+  return render_fwd_impl(f, g, bg, out_feat, out_alpha, stream, false);
+}
+
+tg_status tg_render_fwd_counted(tg_frame* f, const tg_gaussians* g, const float* bg, float* out_feat,
+                                float* out_alpha, void* stream) {
+  return render_fwd_impl(f, g, bg, out_feat, out_alpha, stream, true);
+}
+
+tg_status tg_frame_work(tg_frame* f, int64_t* counts, int32_t n_counts) {
+  if (!f || !counts || n_counts < 0) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  if (hipStreamSynchronize(f->last_stream) != hipSuccess) return TG_ERR_HIP;
+  tg::FrameDev d;
+  if (hipMemcpy(&d, f->dev, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return TG_ERR_HIP;
+  const unsigned long long v[5] = {d.n_eval, d.n_blend, d.wave_steps, d.wave_pass, d.wave_blend};
+  for (int i = 0; i < n_counts && i < 5; ++i) counts[i] = (int64_t)v[i];
+  return TG_OK;
+}
+
+tg_status tg_render_bwd(tg_frame* f, const tg_gaussians* g, const float* bg, const float* d_feat,
+                        const float* d_alpha, const tg_grads* out, void* stream) {
+  if (!f || !f->rendered || !d_feat || !out || !out->d_feat) return TG_ERR_INVALID;
+  tg_status st = check_gaussians(f, g, true);
+  if (st != TG_OK) return st;
+  if (g->n != f->n || g->c != f->c) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  f->last_stream = s;
+  if (tg::launch_fill_zero(f->g2d, 6 * g->n, s) != hipSuccess) return TG_ERR_HIP;
+  if (tg::launch_fill_zero(out->d_feat, g->n * (int64_t)g->c, s) != hipSuccess) return TG_ERR_HIP;
+  tg::BackwardArgs b;
+  b.xy = f->xy; b.conic_o = f->conic_o; b.feat = g->feat;
+  b.tile_start = f->tile_start; b.sorted = f->sorted; b.bg = bg;
+  b.T_final = f->T_final; b.last = f->last;
+  b.d_img = d_feat; b.d_alpha = d_alpha;
+  b.g2d = f->g2d; b.g_feat = out->d_feat;
+  b.n = g->n;
+  b.W = f->cam.W; b.H = f->cam.H; b.tiles_x = f->cam.tiles_x; b.n_tiles = f->n_tiles;
+  b.dev = f->dev;
+  if (tg::launch_render_bwd(b, g->c, s) != hipSuccess) return TG_ERR_HIP;
+  tg::ProjectBwdArgs p;
+  p.mean = g->mean; p.scale = g->scale; p.quat = g->quat; p.opacity = g->opacity;
+  p.n = g->n; p.cam = f->cam; p.rect = f->rect; p.g2d = f->g2d;
+  p.d_mean = out->d_mean; p.d_log_scale = out->d_log_scale; p.d_quat = out->d_quat;
+  p.d_logit = out->d_opacity_logit;
+  if (tg::launch_project_bwd(p, s) != hipSuccess) return TG_ERR_HIP;
+  return TG_OK;
+}
+
+tg_status tg_frame_check(tg_frame* f, int64_t* n_keys) {
+  if (!f) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  if (hipStreamSynchronize(f->last_stream) != hipSuccess) return TG_ERR_HIP;
+  tg::FrameDev d;
+  if (hipMemcpy(&d, f->dev, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return TG_ERR_HIP;
+  if (n_keys) *n_keys = d.n_keys;
+  return d.overflow ? TG_ERR_CAPACITY : TG_OK;
+}
+
+tg_status tg_frame_lists(tg_frame* f, int32_t* tile_start, int32_t* sorted, int64_t n_keys,
+                         void* stream) {
+  if (!f || n_keys < 0 || n_keys > f->max_keys || !f->binned) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (tile_start &&
+      hipMemcpyAsync(tile_start, f->tile_start, ((size_t)f->n_tiles + 1) * sizeof(int32_t),
+                     hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return TG_ERR_HIP;
+  if (sorted && n_keys > 0 &&
+      hipMemcpyAsync(sorted, f->sorted, (size_t)n_keys * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                     s) != hipSuccess)
+    return TG_ERR_HIP;
+  return TG_OK;
+}
+
+tg_status tg_frame_pixel_state(tg_frame* f, float* T_final, int32_t* last, void* stream) {
+  if (!f || !f->rendered) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t npix = (size_t)f->cam.W * f->cam.H;
+  if (T_final && hipMemcpyAsync(T_final, f->T_final, npix * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return TG_ERR_HIP;
+  if (last && hipMemcpyAsync(last, f->last, npix * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return TG_ERR_HIP;
+  return TG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+"""Torch-facing wrapper of libtg: device memory and streams only.
+
+Every step of the rasterizer runs in the HIP kernels behind include/tg.h;
+this module allocates output tensors, passes raw device pointers and the
+current HIP stream, and applies the parameter activations of the
+differentiable path (scale = exp(log_scale), opacity = sigmoid(logit)),
+which the paper's encoder heads produce directly (§4.2, Eq. 4).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+from typing import Optional
+
+import torch
+
+from . import _native as N
+
+__all__ = ["Context", "Frame", "Rasterizer", "rasterize", "camera_struct", "GaussianSoA"]
+
+
+def camera_struct(cam) -> N.tg_camera:
+    """tg_camera from an object (or dict) with R, t, fx, fy, cx, cy, width,
+    height and optional znear."""
+    get = (lambda k, d=None: cam.get(k, d)) if isinstance(cam, dict) else \
+        (lambda k, d=None: getattr(cam, k, d))
+    c = N.tg_camera()
+    R = [float(x) for x in torch.as_tensor(get("R"), dtype=torch.float32).reshape(-1).tolist()]
+    t = [float(x) for x in torch.as_tensor(get("t"), dtype=torch.float32).reshape(-1).tolist()]
+    c.R = (ct.c_float * 9)(*R)
+    c.t = (ct.c_float * 3)(*t)
+    c.fx, c.fy, c.cx, c.cy = float(get("fx")), float(get("fy")), float(get("cx")), float(get("cy"))
+    c.width, c.height = int(get("width")), int(get("height"))
+    c.znear = float(get("znear", 0.2))
+    return c
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libtg takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libtg takes contiguous tensors")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class GaussianSoA:
+    """Structure-of-arrays device tensors of one Gaussian set (float32):
+    mean [3, N], scale [3, N], quat [4, N], opacity [N], feat [N, C]."""
+
+    def __init__(self, mean, scale, quat, opacity, feat):
+        self.mean, self.scale, self.quat = mean, scale, quat
+        self.opacity, self.feat = opacity, feat
+        for t in (mean, scale, quat, opacity, feat):
+            if t.dtype != torch.float32:
+                raise ValueError("float32 tensors expected")
+        self.n = int(mean.shape[1])
+        self.c = int(feat.shape[1])
+
+    @staticmethod
+    def from_scene(scene, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        return GaussianSoA(f(scene.mean), f(scene.scale), f(scene.quat), f(scene.opacity),
+                           f(scene.feat))
+
+    def struct(self) -> N.tg_gaussians:
+        g = N.tg_gaussians()
+        g.mean, g.scale, g.quat = _ptr(self.mean), _ptr(self.scale), _ptr(self.quat)
+        g.opacity, g.feat = _ptr(self.opacity), _ptr(self.feat)
+        g.n, g.c = self.n, self.c
+        return g
+
+
+class Context:
+    _by_device = {}
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        self.handle = N.tg_ctx_create(self.device)
+
+    @classmethod
+    def get(cls, device: int = 0) -> "Context":
+        if device not in cls._by_device:
+            cls._by_device[device] = Context(device)
+        return cls._by_device[device]
+
+
+class Frame:
+    """Resident workspace of one render (see tg_frame_create)."""
+
+    def __init__(self, ctx: Context, max_n: int, max_w: int, max_h: int, max_keys: int):
+        self.ctx = ctx
+        self.max_n, self.max_w, self.max_h, self.max_keys = int(max_n), int(max_w), int(max_h), int(max_keys)
+        self.handle = N.tg_frame_create(ctx.handle, self.max_n, self.max_w, self.max_h, self.max_keys)
+        self.generation = 0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            N.tg_frame_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fits(self, n, w, h, keys=0):
+        return n <= self.max_n and w <= self.max_w and h <= self.max_h and keys <= self.max_keys
+
+
+class Rasterizer:
+    """Runs project -> bin_sort -> render_fwd (and the adjoint) on one frame,
+    growing the frame when a scene needs more room."""
+
+    def __init__(self, device: int = 0, max_n: int = 1 << 16, max_w: int = 256, max_h: int = 256,
+                 keys_per_gaussian: float = 8.0, max_keys: Optional[int] = None):
+        self.device = int(device)
+        self.ctx = Context.get(self.device)
+        self.kpg = float(keys_per_gaussian)
+        self.frame = Frame(self.ctx, max_n, max_w, max_h,
+                           max_keys or max(1024, int(max_n * self.kpg)))
+        self.n_keys = 0
+
+    def _ensure(self, n, w, h, keys=0):
+        f = self.frame
+        if not f.fits(n, w, h, keys):
+            nn, ww, hh = max(n, f.max_n), max(w, f.max_w), max(h, f.max_h)
+            kk = max(keys, f.max_keys, int(nn * self.kpg))
+            f.close()
+            self.frame = Frame(self.ctx, nn, ww, hh, min(kk, (1 << 31) - 1))
+
+    def project_bin(self, g: GaussianSoA, cam, stream=None, check: bool = True):
+        c = camera_struct(cam)
+        self._ensure(g.n, c.width, c.height)
+        s = _stream(stream)
+        gs = g.struct()
+        for _ in range(3):
+            N.check(N.tg_project(self.frame.handle, gs, c, s), "tg_project")
+            N.check(N.tg_bin_sort(self.frame.handle, s), "tg_bin_sort")
+            if not check:
+                return c
+            st, nk = N.tg_frame_check(self.frame.handle)
+            self.n_keys = nk
+            if st == N.TG_OK:
+                return c
+            if st != N.TG_ERR_CAPACITY:
+                N.check(st, "tg_frame_check")
+            self._ensure(g.n, c.width, c.height, int(nk * 1.25) + 1024)
+        raise N.TgError(N.TG_ERR_CAPACITY, "binning")
+
+    def forward(self, g: GaussianSoA, cam, bg: Optional[torch.Tensor] = None, stream=None,
+                check: bool = True, out=None):
+        """Returns (feat [C, H, W], alpha [H, W]) float32 on the device."""
+        c = self.project_bin(g, cam, stream, check)
+        H, W = c.height, c.width
+        dev = g.mean.device
+        if out is None:
+            feat = torch.empty((g.c, H, W), dtype=torch.float32, device=dev)
+            alpha = torch.empty((H, W), dtype=torch.float32, device=dev)
+        else:
+            feat, alpha = out
+        N.check(N.tg_render_fwd(self.frame.handle, g.struct(), _ptr(bg), _ptr(feat), _ptr(alpha),
+                                _stream(stream)), "tg_render_fwd")
+        self.frame.generation += 1
+        return feat, alpha
+
+    def backward(self, g: GaussianSoA, d_feat: torch.Tensor, d_alpha: Optional[torch.Tensor] = None,
+                 bg: Optional[torch.Tensor] = None, stream=None):
+        """Gradients w.r.t. the raw parameters of the last forward, SoA:
+        dict(mean [3, N], log_scale [3, N], quat [4, N], opacity_logit [N],
+        feat [N, C])."""
+        dev = g.mean.device
+        out = dict(mean=torch.empty((3, g.n), dtype=torch.float32, device=dev),
+                   log_scale=torch.empty((3, g.n), dtype=torch.float32, device=dev),
+                   quat=torch.empty((4, g.n), dtype=torch.float32, device=dev),
+                   opacity_logit=torch.empty((g.n,), dtype=torch.float32, device=dev),
+                   feat=torch.empty((g.n, g.c), dtype=torch.float32, device=dev))
+        gr = N.tg_grads()
+        gr.d_mean, gr.d_log_scale, gr.d_quat = _ptr(out["mean"]), _ptr(out["log_scale"]), _ptr(out["quat"])
+        gr.d_opacity_logit, gr.d_feat = _ptr(out["opacity_logit"]), _ptr(out["feat"])
+        N.check(N.tg_render_bwd(self.frame.handle, g.struct(), _ptr(bg), _ptr(d_feat.contiguous()),
+                                _ptr(None if d_alpha is None else d_alpha.contiguous()), gr,
+                                _stream(stream)), "tg_render_bwd")
+        return out
+
+    # -------------------------------------------------------- introspection
+    def tile_lists(self, cam, stream=None):
+        """(tile_start [n_tiles + 1], sorted [K]) int32 device copies of the last binning."""
+        c = camera_struct(cam)
+        nt = ((c.width + 15) // 16) * ((c.height + 15) // 16)
+        st, nk = N.tg_frame_check(self.frame.handle)
+        N.check(st, "tg_frame_check")
+        dev = torch.device("cuda", self.device)
+        ts = torch.empty(nt + 1, dtype=torch.int32, device=dev)
+        so = torch.empty(max(nk, 1), dtype=torch.int32, device=dev)
+        N.check(N.tg_frame_lists(self.frame.handle, _ptr(ts), _ptr(so), nk, _stream(stream)), "tg_frame_lists")
+        return ts, so[:nk]
+
+    def pixel_state(self, cam, stream=None):
+        """(T_final [H, W] float32, last [H, W] int32) device copies of the last forward."""
+        c = camera_struct(cam)
+        dev = torch.device("cuda", self.device)
+        T = torch.empty((c.height, c.width), dtype=torch.float32, device=dev)
+        last = torch.empty((c.height, c.width), dtype=torch.int32, device=dev)
+        N.check(N.tg_frame_pixel_state(self.frame.handle, _ptr(T), _ptr(last), _stream(stream)),
+                "tg_frame_pixel_state")
+        return T, last
+
+
+class _RasterizeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, feats, rast, cam, bg):
+        g = GaussianSoA(means.detach().t().contiguous(), torch.exp(log_scales.detach()).t().contiguous(),
+                        quats.detach().t().contiguous(), torch.sigmoid(opacity_logits.detach()).contiguous(),
+                        feats.detach().contiguous())
+        img, alpha = rast.forward(g, cam, bg)
+        ctx.rast, ctx.g, ctx.bg = rast, g, bg
+        ctx.generation = rast.frame.generation
+        ctx.frame = rast.frame
+        ctx.hw = tuple(alpha.shape)
+        return img, alpha
+
+    @staticmethod
+    def backward(ctx, d_img, d_alpha):
+        rast = ctx.rast
+        if rast.frame is not ctx.frame or rast.frame.generation != ctx.generation:
+            raise RuntimeError("the rasterizer rendered again before this backward; "
+                               "use one Rasterizer per in-flight differentiable render")
+        if d_img is None:
+            d_img = torch.zeros((ctx.g.c,) + ctx.hw, device=ctx.g.mean.device)
+        gr = rast.backward(ctx.g, d_img.float().contiguous(),
+                           None if d_alpha is None else d_alpha.float().contiguous(), ctx.bg)
+        return (gr["mean"].t(), gr["log_scale"].t(), gr["quat"].t(), gr["opacity_logit"],
+                gr["feat"], None, None, None)
+
+
+def rasterize(means: torch.Tensor, log_scales: torch.Tensor, quats: torch.Tensor,
+              opacity_logits: torch.Tensor, feats: torch.Tensor, cam, bg: Optional[torch.Tensor] = None,
+              rasterizer: Optional[Rasterizer] = None):
+    """F_novel = R_G({G}, Pi_novel) (§4.2) with gradients.
+
+    means [N, 3], log_scales [N, 3], quats [N, 4] (w, x, y, z), opacity_logits
+    [N], feats [N, C] (C in 8, 16, 32, 64) -> (feat [C, H, W], alpha [H, W])."""
+    if rasterizer is None:
+        dev = means.device.index or 0
+        c = camera_struct(cam)
+        rasterizer = Rasterizer(dev, max_n=max(1, means.shape[0]), max_w=c.width, max_h=c.height)
+    return _RasterizeFn.apply(means, log_scales, quats, opacity_logits, feats, rasterizer, cam, bg)
