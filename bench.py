@@ -32,7 +32,23 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="bound on the oracle's timed CPU work")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain device copy of known size (scale for HBM counters)")
     return p.parse_args()
+
+
+def copy_calibration():
+    """A plain 256 MiB device-to-device copy, three times: the FETCH_SIZE /
+    WRITE_SIZE counters of this kernel divided by its 256 MiB give the
+    factor that converts those counters into HBM bytes."""
+    import torch
+    n = 64 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "repeats": 3}), flush=True)
 
 
 def pct(xs, q):
@@ -67,6 +83,9 @@ def cpu_baseline(scene, budget_s):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
                           "described in DESIGN.md but not built", "n_gpus": args.gpus}))

@@ -186,6 +186,85 @@ tg_status tg_frame_lists(tg_frame* frame, int32_t* tile_start, int32_t* sorted, 
  * -1 if none).  Either output may be NULL. */
 tg_status tg_frame_pixel_state(tg_frame* frame, float* T_final, int32_t* last, void* stream);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop that renders many target views at once (the system of §5.3
+ * renders every frame of every terminal through R_G, under CUDA Graphs).
+ * Requests of uneven Gaussian counts and resolutions are admitted first in,
+ * first out while the device bytes of the requests in flight stay within a
+ * budget; whenever a slot is free, all admitted requests (up to max_batch)
+ * form one batch that runs as a single persistent launch of every step,
+ * replayed from a HIP graph captured once per slot.  Slots run on their own
+ * streams, so a batch formed while others are on the GPU overlaps with
+ * them.  Each request's result is the same as when rendered alone. */
+
+typedef struct tg_serve_opts {
+  int64_t budget_bytes;         /* device bytes the requests in flight may occupy */
+  int32_t slots;                /* batches in flight at once (one HIP stream each), 1..8 */
+  int32_t max_batch;            /* requests per batch, 1..64 */
+  int64_t max_gauss_per_batch;  /* slot workspace: Gaussians (sum over the batch) */
+  int64_t max_keys_per_batch;   /* slot workspace: (tile, Gaussian) keys */
+  int64_t max_pixels_per_batch; /* slot workspace: target pixels */
+  int32_t max_side;             /* largest target width or height accepted */
+  int32_t c;                    /* channel count of every request: 8, 16, 32 or 64 */
+  int32_t use_graph;            /* 1: replay a captured HIP graph per slot; 0: launch directly */
+  float keys_per_gaussian;      /* key estimate per Gaussian used for admission */
+} tg_serve_opts;
+
+/* One render request.  g points at device buffers that the caller keeps
+ * resident (for instance the stream's arena from tg_serve_stream_arena) and
+ * must not modify until the request is done; out_feat [c][H][W] and
+ * out_alpha [H][W] (or NULL) are device buffers the caller owns. */
+typedef struct tg_request {
+  int32_t stream_id;
+  tg_gaussians g;
+  tg_camera cam;
+  const float* bg;              /* [c] or NULL */
+  float* out_feat;
+  float* out_alpha;
+} tg_request;
+
+typedef struct tg_result {
+  int32_t status;               /* TG_OK, TG_PENDING or an error code */
+  int32_t batch_size;           /* requests in the batch that rendered it */
+  int32_t slot;
+  int32_t retries;              /* re-admissions after a key-capacity overflow */
+  int64_t t_submit_ns;          /* host steady clock, nanoseconds */
+  int64_t t_launch_ns;
+  int64_t t_done_ns;            /* when the server observed completion */
+} tg_result;
+
+/* Create a server: allocates every slot's workspace, creates the slot
+ * streams and, with use_graph, captures one graph per slot.  Starts the
+ * scheduler thread. */
+tg_status tg_serve_create(tg_ctx* ctx, const tg_serve_opts* opts /* host */, tg_server** out);
+
+/* Device buffers for the Gaussians of stream `stream_id`, allocated on the
+ * first call (max_n Gaussians, the server's c channels) and kept for the
+ * server's lifetime; later calls return the same buffers (max_n must not
+ * grow).  Their bytes count against the budget for as long as they exist.
+ * *out (host) receives the pointers with n = max_n. */
+tg_status tg_serve_stream_arena(tg_server* srv, int32_t stream_id, int64_t max_n,
+                                tg_gaussians* out /* host */);
+
+/* Thread-safe, non-blocking: queue a request; *ticket (host) identifies it.
+ * TG_ERR_BUDGET if the request alone can never fit a slot or the budget. */
+tg_status tg_serve_submit(tg_server* srv, const tg_request* req /* host */, uint64_t* ticket);
+
+/* Non-blocking: TG_PENDING while queued or in flight, else the request's
+ * final status; *out (host, may be NULL) receives its record.  A finished
+ * ticket stays readable until tg_serve_release. */
+tg_status tg_serve_poll(tg_server* srv, uint64_t ticket, tg_result* out);
+
+/* Blocks until the ticket is finished; returns its final status. */
+tg_status tg_serve_wait(tg_server* srv, uint64_t ticket, tg_result* out);
+
+/* Forget a finished ticket. */
+tg_status tg_serve_release(tg_server* srv, uint64_t ticket);
+
+/* Stops the scheduler after the requests in flight finish (queued requests
+ * are dropped with TG_ERR_INVALID) and frees every resource. */
+void tg_serve_destroy(tg_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,8 @@ EXPORTS = [
     "tg_status_string", "tg_ctx_create", "tg_ctx_destroy", "tg_frame_create",
     "tg_frame_destroy", "tg_project", "tg_bin_sort", "tg_render_fwd", "tg_render_bwd",
     "tg_frame_check", "tg_frame_lists", "tg_frame_pixel_state", "tg_render_fwd_counted",
-    "tg_frame_work",
+    "tg_frame_work", "tg_serve_create", "tg_serve_stream_arena", "tg_serve_submit",
+    "tg_serve_poll", "tg_serve_wait", "tg_serve_release", "tg_serve_destroy",
 ]
 
 
@@ -48,6 +49,24 @@ class tg_grads(ct.Structure):
     _fields_ = [("d_mean", ct.c_void_p), ("d_log_scale", ct.c_void_p),
                 ("d_quat", ct.c_void_p), ("d_opacity_logit", ct.c_void_p),
                 ("d_feat", ct.c_void_p)]
+
+
+class tg_serve_opts(ct.Structure):
+    _fields_ = [("budget_bytes", ct.c_int64), ("slots", ct.c_int32), ("max_batch", ct.c_int32),
+                ("max_gauss_per_batch", ct.c_int64), ("max_keys_per_batch", ct.c_int64),
+                ("max_pixels_per_batch", ct.c_int64), ("max_side", ct.c_int32), ("c", ct.c_int32),
+                ("use_graph", ct.c_int32), ("keys_per_gaussian", ct.c_float)]
+
+
+class tg_request(ct.Structure):
+    _fields_ = [("stream_id", ct.c_int32), ("g", tg_gaussians), ("cam", tg_camera),
+                ("bg", ct.c_void_p), ("out_feat", ct.c_void_p), ("out_alpha", ct.c_void_p)]
+
+
+class tg_result(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("batch_size", ct.c_int32), ("slot", ct.c_int32),
+                ("retries", ct.c_int32), ("t_submit_ns", ct.c_int64), ("t_launch_ns", ct.c_int64),
+                ("t_done_ns", ct.c_int64)]
 
 
 class TgError(RuntimeError):
@@ -87,6 +106,19 @@ def lib():
     L.tg_render_fwd_counted.argtypes = [P, ct.POINTER(tg_gaussians), P, P, P, P]
     L.tg_frame_work.restype = I
     L.tg_frame_work.argtypes = [P, ct.POINTER(I64), I32]
+    L.tg_serve_create.restype = I
+    L.tg_serve_create.argtypes = [P, ct.POINTER(tg_serve_opts), ct.POINTER(P)]
+    L.tg_serve_stream_arena.restype = I
+    L.tg_serve_stream_arena.argtypes = [P, I32, I64, ct.POINTER(tg_gaussians)]
+    L.tg_serve_submit.restype = I
+    L.tg_serve_submit.argtypes = [P, ct.POINTER(tg_request), ct.POINTER(ct.c_uint64)]
+    L.tg_serve_poll.restype = I
+    L.tg_serve_poll.argtypes = [P, ct.c_uint64, ct.POINTER(tg_result)]
+    L.tg_serve_wait.restype = I
+    L.tg_serve_wait.argtypes = [P, ct.c_uint64, ct.POINTER(tg_result)]
+    L.tg_serve_release.restype = I
+    L.tg_serve_release.argtypes = [P, ct.c_uint64]
+    L.tg_serve_destroy.argtypes = [P]
     L.tg_render_bwd.restype = I
     L.tg_render_bwd.argtypes = [P, ct.POINTER(tg_gaussians), P, P, P, ct.POINTER(tg_grads), P]
     L.tg_frame_check.restype = I
@@ -173,3 +205,43 @@ def tg_frame_lists(frame: int, tile_start: int, sorted_: int, n_keys: int, strea
 
 def tg_frame_pixel_state(frame: int, T_final: int, last: int, stream: int) -> int:
     return lib().tg_frame_pixel_state(frame, T_final, last, stream)
+
+
+def tg_serve_create(ctx: int, opts: tg_serve_opts) -> int:
+    out = ct.c_void_p()
+    check(lib().tg_serve_create(ctx, ct.byref(opts), ct.byref(out)), "tg_serve_create")
+    return out.value
+
+
+def tg_serve_stream_arena(srv: int, stream_id: int, max_n: int) -> tg_gaussians:
+    g = tg_gaussians()
+    check(lib().tg_serve_stream_arena(srv, int(stream_id), int(max_n), ct.byref(g)),
+          "tg_serve_stream_arena")
+    return g
+
+
+def tg_serve_submit(srv: int, req: tg_request):
+    """(status, ticket)"""
+    t = ct.c_uint64(0)
+    st = lib().tg_serve_submit(srv, ct.byref(req), ct.byref(t))
+    return st, int(t.value)
+
+
+def tg_serve_poll(srv: int, ticket: int):
+    r = tg_result()
+    st = lib().tg_serve_poll(srv, ct.c_uint64(ticket), ct.byref(r))
+    return st, r
+
+
+def tg_serve_wait(srv: int, ticket: int):
+    r = tg_result()
+    st = lib().tg_serve_wait(srv, ct.c_uint64(ticket), ct.byref(r))
+    return st, r
+
+
+def tg_serve_release(srv: int, ticket: int) -> int:
+    return lib().tg_serve_release(srv, ct.c_uint64(ticket))
+
+
+def tg_serve_destroy(srv: int) -> None:
+    lib().tg_serve_destroy(srv)

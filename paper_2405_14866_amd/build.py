@@ -2,8 +2,9 @@
 
 hipcc compiles every csrc/*.hip file with -ffp-contract=off (the float32
 binning spec must see each IEEE operation as written; the kernels use
-explicit fma where they want one) and with packed-FP32 instruction
-selection disabled, then links one shared library next to this file.
+explicit fma where they want one), with packed-FP32 instruction selection
+disabled and with MFMA accumulators kept in VGPRs, then links one shared
+library next to this file.
 """
 import os
 import shutil
@@ -19,6 +20,8 @@ ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # keep MFMA accumulators in ordinary VGPRs (no AGPR round trips)
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I", os.path.join(HERE, "..", "include")]
 

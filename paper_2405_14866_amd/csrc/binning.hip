@@ -20,8 +20,10 @@
 //            8-bit digits (ranking within each wave64 by ballot matching,
 //            digit offsets by a wave-level scan, four barriers per pass) on
 //            the depth bits alone, re-based to the segment's minimum (about
-//            three passes); only a segment that holds two equal depths is
-//            sorted again on the composite (depth - min, index - min) key.
+//            three passes); runs of equal depth (frequent: a tile spans a
+//            narrow depth range) are then ordered by index, one lane per
+//            run, and only a run longer than 32 sends the tile to a sort on
+//            the composite (depth - min, index - min) key.
 //            Either way the result is the unique (depth, index) order.
 //            Segments up to 2048 keys run in a 32 KB-LDS launch (four
 //            workgroups per CU), larger ones in a second launch with 128 KB,
@@ -39,41 +41,69 @@ __device__ __forceinline__ void rect_of(uint2 r, int& x0, int& x1, int& y0, int&
   y0 = (int)(r.y & 0xffffu); y1 = (int)(r.y >> 16);
 }
 
-template <bool LDS_BINS>
-__global__ void __launch_bounds__(1024) k_count(BinArgs a) {
+// The workgroup's request: chunk [g0, g0 + BIN_CHUNK) of the padded index space.
+struct ChunkReq {
+  int r;
+  int64_t i0, i1;      // local Gaussian range of the chunk
+  int64_t g_off;
+  int tiles_x, n_tiles, tile_off;
+};
+
+__device__ __forceinline__ bool chunk_req(const BatchArgs& a, const BatchHdr& h, ChunkReq& c) {
+  const int64_t g0 = (int64_t)blockIdx.x * BIN_CHUNK;
+  c.r = req_of_gauss(a, h, g0);
+  if (c.r < 0) return false;
+  const ReqDev& q = batch_req(a, c.r);
+  c.g_off = q.g_off;
+  c.i0 = g0 - q.g_off;
+  c.i1 = min(q.n, c.i0 + BIN_CHUNK);
+  c.tiles_x = q.cam.tiles_x;
+  c.n_tiles = q.cam.tiles_x * q.cam.tiles_y;
+  c.tile_off = q.tile_off;
+  return c.i0 < c.i1;
+}
+
+// Per-tile key counts of one chunk: LDS counters for the request's tiles
+// (when they fit), then one global atomic per touched tile.
+__global__ void __launch_bounds__(1024) k_count(BatchArgs a) {
   extern __shared__ int32_t bins[];
+  const BatchHdr h = batch_hdr(a);
+  ChunkReq c;
+  if (!chunk_req(a, h, c)) return;
   const int tid = threadIdx.x;
-  if (LDS_BINS) {
-    for (int t = tid; t < a.n_tiles; t += 1024) bins[t] = 0;
+  const bool lds = c.n_tiles <= BIN_LDS_MAX_TILES;
+  int32_t* gcount = a.tile_count + c.tile_off;
+  if (lds) {
+    for (int t = tid; t < c.n_tiles; t += 1024) bins[t] = 0;
     __syncthreads();
   }
-  const int64_t g0 = (int64_t)blockIdx.x * BIN_CHUNK;
-  const int64_t g1 = min(a.n, g0 + BIN_CHUNK);
-  for (int64_t g = g0 + tid; g < g1; g += 1024) {
+  for (int64_t i = c.i0 + tid; i < c.i1; i += 1024) {
     int x0, x1, y0, y1;
-    rect_of(a.rect[g], x0, x1, y0, y1);
+    rect_of(a.rect[c.g_off + i], x0, x1, y0, y1);
     for (int ty = y0; ty <= y1; ++ty)
       for (int tx = x0; tx <= x1; ++tx) {
-        const int t = ty * a.tiles_x + tx;
-        if (LDS_BINS) atomicAdd(&bins[t], 1);
-        else atomicAdd(&a.tile_count[t], 1);
+        const int t = ty * c.tiles_x + tx;
+        if (lds) atomicAdd(&bins[t], 1);
+        else atomicAdd(&gcount[t], 1);
       }
   }
-  if (LDS_BINS) {
+  if (lds) {
     __syncthreads();
-    for (int t = tid; t < a.n_tiles; t += 1024) {
+    for (int t = tid; t < c.n_tiles; t += 1024) {
       const int v = bins[t];
-      if (v) atomicAdd(&a.tile_count[t], v);
+      if (v) atomicAdd(&gcount[t], v);
     }
   }
 }
 
-// exclusive scan of tile counts (one workgroup of 1024 lanes)
-__global__ void __launch_bounds__(1024) k_scan(BinArgs a) {
+// exclusive scan of the batch's tile counts (one workgroup of 1024 lanes)
+__global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
   __shared__ int64_t part[1024];
+  const BatchHdr h = batch_hdr(a);
+  const int nt = h.n_tiles;
   const int tid = threadIdx.x;
-  const int per = (a.n_tiles + 1023) / 1024;
-  const int b = min(a.n_tiles, tid * per), e = min(a.n_tiles, b + per);
+  const int per = (nt + 1023) / 1024;
+  const int b = min(nt, tid * per), e = min(nt, b + per);
   int64_t sum = 0;
   for (int t = b; t < e; ++t) sum += a.tile_count[t];
   part[tid] = sum;
@@ -94,45 +124,50 @@ __global__ void __launch_bounds__(1024) k_scan(BinArgs a) {
     run += a.tile_count[t];
   }
   if (tid == 1023) {
-    a.tile_start[a.n_tiles] = over ? 0 : (int32_t)total;
+    a.tile_start[nt] = over ? 0 : (int32_t)total;
     a.dev->n_keys = total;
     a.dev->overflow = over ? 1 : 0;
   }
 }
 
-template <bool LDS_BINS>
-__global__ void __launch_bounds__(1024) k_fill(BinArgs a) {
+// Scatter of one chunk's keys into the tile segments: LDS counts, one
+// global atomic per touched tile reserves a run, LDS atomics hand out the
+// slots of the run.
+__global__ void __launch_bounds__(1024) k_fill(BatchArgs a) {
   if (a.dev->overflow) return;
   extern __shared__ int32_t bins[];
+  const BatchHdr h = batch_hdr(a);
+  ChunkReq c;
+  if (!chunk_req(a, h, c)) return;
   const int tid = threadIdx.x;
-  const int64_t g0 = (int64_t)blockIdx.x * BIN_CHUNK;
-  const int64_t g1 = min(a.n, g0 + BIN_CHUNK);
-  if (LDS_BINS) {
-    for (int t = tid; t < a.n_tiles; t += 1024) bins[t] = 0;
+  const bool lds = c.n_tiles <= BIN_LDS_MAX_TILES;
+  int32_t* gcursor = a.tile_cursor + c.tile_off;
+  if (lds) {
+    for (int t = tid; t < c.n_tiles; t += 1024) bins[t] = 0;
     __syncthreads();
-    for (int64_t g = g0 + tid; g < g1; g += 1024) {
+    for (int64_t i = c.i0 + tid; i < c.i1; i += 1024) {
       int x0, x1, y0, y1;
-      rect_of(a.rect[g], x0, x1, y0, y1);
+      rect_of(a.rect[c.g_off + i], x0, x1, y0, y1);
       for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) atomicAdd(&bins[ty * a.tiles_x + tx], 1);
+        for (int tx = x0; tx <= x1; ++tx) atomicAdd(&bins[ty * c.tiles_x + tx], 1);
     }
     __syncthreads();
-    // reserve this workgroup's run inside every touched tile segment
-    for (int t = tid; t < a.n_tiles; t += 1024) {
+    for (int t = tid; t < c.n_tiles; t += 1024) {
       const int v = bins[t];
-      if (v) bins[t] = atomicAdd(&a.tile_cursor[t], v);
+      if (v) bins[t] = atomicAdd(&gcursor[t], v);
     }
     __syncthreads();
   }
-  for (int64_t g = g0 + tid; g < g1; g += 1024) {
+  for (int64_t i = c.i0 + tid; i < c.i1; i += 1024) {
+    const int64_t g = c.g_off + i;
     int x0, x1, y0, y1;
     rect_of(a.rect[g], x0, x1, y0, y1);
     if (x0 > x1) continue;
     const uint64_t key = ((uint64_t)a.depth[g] << 32) | (uint64_t)(uint32_t)g;
     for (int ty = y0; ty <= y1; ++ty)
       for (int tx = x0; tx <= x1; ++tx) {
-        const int t = ty * a.tiles_x + tx;
-        const int slot = LDS_BINS ? atomicAdd(&bins[t], 1) : atomicAdd(&a.tile_cursor[t], 1);
+        const int t = ty * c.tiles_x + tx;
+        const int slot = lds ? atomicAdd(&bins[t], 1) : atomicAdd(&gcursor[t], 1);
         a.keys[slot] = key;
       }
   }
@@ -246,15 +281,19 @@ __device__ __forceinline__ Ptr radix_sort(Ptr a, Ptr b, int n, int shift0, int b
   return a;
 }
 
+constexpr int MAX_TIE_RUN = 32;
+
 // Segment sort of tiles whose key count lies in (lo, hi]: sort by depth
-// alone (the key's high half, re-based to its minimum) and, only if two
-// keys of the segment have the same depth, redo it on the composite
-// (depth, index) key.  Either way the result is the (depth, index) order.
-// Segments above CAP run the composite sort on the global scratch buffers.
+// alone (the key's high half, re-based to its minimum), then order each run
+// of equal depths by index; only a run longer than MAX_TIE_RUN makes the
+// tile redo the sort on the composite (depth, index) key.  Either way the
+// result is the (depth, index) order.  Segments above CAP run the
+// composite sort on the global scratch buffers.
 template <int CAP>
-__global__ void __launch_bounds__(256) k_sort(BinArgs a, int lo, int hi) {
+__global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
   if (a.dev->overflow) return;
   const int t = blockIdx.x;
+  if (t >= batch_hdr(a).n_tiles) return;
   const int s = a.tile_start[t], e = a.tile_start[t + 1];
   const int n = e - s;
   if (n <= lo || n > hi) return;
@@ -293,9 +332,25 @@ __global__ void __launch_bounds__(256) k_sort(BinArgs a, int lo, int hi) {
     }
     __syncthreads();
     uint64_t* res = radix_sort<uint64_t*>(bufA, bufB, n, 32, db, sh);
-    int tie = 0;
-    for (int j = tid; j + 1 < n; j += 256) tie |= (res[j] >> 32) == (res[j + 1] >> 32);
-    if (__syncthreads_or(tie)) {
+    // Equal depths are now adjacent, in arbitrary order.  A lane per run of
+    // equal depths orders it by index (insertion sort, runs are short); a
+    // run longer than MAX_TIE_RUN sends the tile to the composite sort.
+    int too_long = 0;
+    for (int j = tid; j < n; j += 256) {
+      const uint64_t dj = res[j] >> 32;
+      const bool start = (j == 0 || (res[j - 1] >> 32) != dj) && j + 1 < n && (res[j + 1] >> 32) == dj;
+      if (!start) continue;
+      int end = j + 1;
+      while (end < n && (res[end] >> 32) == dj && end - j <= MAX_TIE_RUN) ++end;
+      if (end - j > MAX_TIE_RUN) { too_long = 1; continue; }
+      for (int p = j + 1; p < end; ++p) {        // same depth: compare the index half
+        const uint64_t v = res[p];
+        int q = p - 1;
+        while (q >= j && res[q] > v) { res[q + 1] = res[q]; --q; }
+        res[q + 1] = v;
+      }
+    }
+    if (__syncthreads_or(too_long)) {
       for (int j = tid; j < n; j += 256) {
         const uint64_t k = a.keys[s + j];
         bufA[j] = (((k >> 32) - dmin) << ib) | ((k & 0xffffffffull) - imin);
@@ -321,33 +376,30 @@ constexpr int SORT_LARGE = 8192;   // larger segments: 128 KB of LDS keys, beyon
 
 }  // namespace
 
-hipError_t launch_bin_sort(const BinArgs& a, hipStream_t s) {
-  const int64_t chunks = (a.n + BIN_CHUNK - 1) / BIN_CHUNK;
+hipError_t launch_bin_sort(const BatchArgs& a, int64_t grid_gauss, int32_t grid_tiles,
+                           int32_t max_tiles_per_req, hipStream_t s) {
+  const int64_t chunks = (grid_gauss + BIN_CHUNK - 1) / BIN_CHUNK;
   const int grid = (int)(chunks > 0 ? chunks : 1);
-  const bool lds = a.n_tiles <= BIN_LDS_MAX_TILES;
-  const size_t shm = lds ? (size_t)a.n_tiles * sizeof(int32_t) : 0;
-  if (lds) hipLaunchKernelGGL(k_count<true>, dim3(grid), dim3(1024), shm, s, a);
-  else hipLaunchKernelGGL(k_count<false>, dim3(grid), dim3(1024), 0, s, a);
+  const size_t shm = (size_t)min(max_tiles_per_req, BIN_LDS_MAX_TILES) * sizeof(int32_t);
+  const int gt = grid_tiles > 0 ? grid_tiles : 1;
+  hipLaunchKernelGGL(k_count, dim3(grid), dim3(1024), shm, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  if (lds) hipLaunchKernelGGL(k_fill<true>, dim3(grid), dim3(1024), shm, s, a);
-  else hipLaunchKernelGGL(k_fill<false>, dim3(grid), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(1024), shm, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(k_sort<SORT_SMALL>, dim3(a.n_tiles), dim3(256), 0, s, a, 0, SORT_SMALL);
+  hipLaunchKernelGGL(k_sort<SORT_SMALL>, dim3(gt), dim3(256), 0, s, a, 0, SORT_SMALL);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(k_sort<SORT_LARGE>, dim3(a.n_tiles), dim3(256), 0, s, a, SORT_SMALL, 0x7fffffff);
+  hipLaunchKernelGGL(k_sort<SORT_LARGE>, dim3(gt), dim3(256), 0, s, a, SORT_SMALL, 0x7fffffff);
   return hipGetLastError();
 }
 
 hipError_t bin_set_attributes() {
   const int bytes = BIN_LDS_MAX_TILES * (int)sizeof(int32_t);
-  hipError_t e = hipFuncSetAttribute((const void*)k_count<true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipError_t e = hipFuncSetAttribute((const void*)k_count, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_fill<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             bytes);
+  return hipFuncSetAttribute((const void*)k_fill, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 }  // namespace tg

@@ -2,7 +2,9 @@
 //
 // One lane per Gaussian, structure-of-arrays loads (each of the 11 input
 // streams is read with unit stride, so every wave issues fully coalesced
-// 256-byte reads).  The kernel does two things per Gaussian:
+// 256-byte reads); a workgroup covers 256 aligned indices of the batch's
+// padded Gaussian index space, hence one request.  The kernel does two
+// things per Gaussian:
 //
 //  * the float32 "binning spec": view transform, quaternion rotation,
 //    Sigma3D, EWA Sigma2D = (J W) Sigma3D (J W)^T, the 0.3 px^2 dilation,
@@ -93,24 +95,30 @@ __device__ __forceinline__ Rect spec_f32(const CamArgs& c, float mx, float my, f
   return out;
 }
 
-__global__ void __launch_bounds__(256) k_project(ProjectArgs a) {
+__global__ void __launch_bounds__(256) k_project(BatchArgs a) {
+  const BatchHdr h = batch_hdr(a);
   // clear the per-tile key counters that the binning accumulates into
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < a.n_tiles; t += gridDim.x * 256) a.tile_count[t] = 0;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
-  const int64_t n = a.n;
-  const float mx = a.mean[i], my = a.mean[n + i], mz = a.mean[2 * n + i];
-  const float sx = a.scale[i], sy = a.scale[n + i], sz = a.scale[2 * n + i];
-  const float qw = a.quat[i], qx = a.quat[n + i], qy = a.quat[2 * n + i], qz = a.quat[3 * n + i];
-  const float op = a.opacity[i];
-  const Rect r = spec_f32(a.cam, mx, my, mz, sx, sy, sz, qw, qx, qy, qz);
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < h.n_tiles; t += gridDim.x * 256) a.tile_count[t] = 0;
+  const int64_t g0 = (int64_t)blockIdx.x * 256;       // 256-aligned: one request per workgroup
+  const int r = req_of_gauss(a, h, g0);
+  if (r < 0) return;
+  const ReqDev& q = batch_req(a, r);
+  const int64_t gi = g0 + threadIdx.x;
+  const int64_t i = gi - q.g_off;
+  const int64_t n = q.n;
+  if (i >= n) return;
+  const float mx = q.mean[i], my = q.mean[n + i], mz = q.mean[2 * n + i];
+  const float sx = q.scale[i], sy = q.scale[n + i], sz = q.scale[2 * n + i];
+  const float qw = q.quat[i], qx = q.quat[n + i], qy = q.quat[2 * n + i], qz = q.quat[3 * n + i];
+  const float op = q.opacity[i];
+  const CamArgs& c = q.cam;
+  const Rect rc = spec_f32(c, mx, my, mz, sx, sy, sz, qw, qx, qy, qz);
 
   uint2 rect = make_uint2(1u, 0u);   // empty
   double2 xy = make_double2(0.0, 0.0);
   float4 co = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (r.ok) {
+  if (rc.ok) {
     // continuous state in FP64
-    const CamArgs& c = a.cam;
     const double X = mx, Y = my, Z = mz;
     const double tx = (double)c.R[0] * X + (double)c.R[1] * Y + (double)c.R[2] * Z + (double)c.t[0];
     const double ty = (double)c.R[3] * X + (double)c.R[4] * Y + (double)c.R[5] * Z + (double)c.t[1];
@@ -127,8 +135,8 @@ __global__ void __launch_bounds__(256) k_project(ProjectArgs a) {
     const double s2[3] = {(double)sx * sx, (double)sy * sy, (double)sz * sz};
     double S[3][3];
     for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q)
-        S[p][q] = Rq[p][0] * s2[0] * Rq[q][0] + Rq[p][1] * s2[1] * Rq[q][1] + Rq[p][2] * s2[2] * Rq[q][2];
+      for (int k = 0; k < 3; ++k)
+        S[p][k] = Rq[p][0] * s2[0] * Rq[k][0] + Rq[p][1] * s2[1] * Rq[k][1] + Rq[p][2] * s2[2] * Rq[k][2];
     const double j00 = fx / tz, j02 = -fx * tx / (tz * tz), j11 = fy / tz, j12 = -fy * ty / (tz * tz);
     double A[2][3];
     for (int k = 0; k < 3; ++k) {
@@ -137,26 +145,26 @@ __global__ void __launch_bounds__(256) k_project(ProjectArgs a) {
     }
     double AS[2][3];
     for (int p = 0; p < 2; ++p)
-      for (int q = 0; q < 3; ++q) AS[p][q] = A[p][0] * S[0][q] + A[p][1] * S[1][q] + A[p][2] * S[2][q];
+      for (int k = 0; k < 3; ++k) AS[p][k] = A[p][0] * S[0][k] + A[p][1] * S[1][k] + A[p][2] * S[2][k];
     const double sa = AS[0][0] * A[0][0] + AS[0][1] * A[0][1] + AS[0][2] * A[0][2] + 0.3;
     const double sb = AS[0][0] * A[1][0] + AS[0][1] * A[1][1] + AS[0][2] * A[1][2];
     const double sc = AS[1][0] * A[1][0] + AS[1][1] * A[1][1] + AS[1][2] * A[1][2] + 0.3;
     const double det = sa * sc - sb * sb;
     if (det > 0.0) {
       co = make_float4((float)(sc / det), (float)(-sb / det), (float)(sa / det), op);
-      rect = make_uint2((uint32_t)r.x0 | ((uint32_t)r.x1 << 16), (uint32_t)r.y0 | ((uint32_t)r.y1 << 16));
+      rect = make_uint2((uint32_t)rc.x0 | ((uint32_t)rc.x1 << 16), (uint32_t)rc.y0 | ((uint32_t)rc.y1 << 16));
     }
   }
-  a.xy[i] = xy;
-  a.conic_o[i] = co;
-  a.rect[i] = rect;
-  a.depth[i] = r.ok ? r.key : 0xffffffffu;
+  a.xy[gi] = xy;
+  a.conic_o[gi] = co;
+  a.rect[gi] = rect;
+  a.depth[gi] = rc.ok ? rc.key : 0xffffffffu;
 }
 
 }  // namespace
 
-hipError_t launch_project(const ProjectArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.n + 255) / 256;
+hipError_t launch_project(const BatchArgs& a, int64_t grid_gauss, hipStream_t s) {
+  const int64_t blocks = (grid_gauss + 255) / 256;
   const int grid = (int)(blocks > 0 ? blocks : 1);
   hipLaunchKernelGGL(k_project, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();

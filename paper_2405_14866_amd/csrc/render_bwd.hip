@@ -69,44 +69,48 @@ __device__ __forceinline__ bool reduce_writer(int lane) {
 }
 
 template <int C, int BATCH>
-__global__ void __launch_bounds__(256) k_render_bwd(BackwardArgs a) {
-  if (a.dev->overflow) return;
-  const int tile = blockIdx.x;
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+struct BwdShared {
+  float4 sg[BATCH];     // u, v (tile-local), opacity, log2 threshold
+  float4 sq[BATCH];     // scaled conic (as in the forward)
+  float4 sc[BATCH];     // unscaled conic A, B, C
+  int32_t sidx[BATCH];
+  __align__(16) float sf[BATCH][C + 4];
+  float r2d[4][BATCH][8];
+  float rft[4][BATCH][C];
+  int32_t rflag[4][BATCH];
+  int32_t smax;
+};
+
+template <int C, int BATCH>
+__device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, int gtile, int tx, int ty,
+                                         BwdShared<C, BATCH>& sh) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int lx = ((w & 1) << 3) | (lane & 7);
   const int ly = ((w >> 1) << 3) | (lane >> 3);
+  const int W = q.cam.W, H = q.cam.H;
   const int px = tx * TILE + lx, py = ty * TILE + ly;
-  const bool inside = px < a.W && py < a.H;
+  const bool inside = px < W && py < H;
   const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
   const double ox = (double)(tx * TILE), oy = (double)(ty * TILE);
-  const int s = a.tile_start[tile];
+  const int s = a.tile_start[gtile];
+  auto& sg = sh.sg; auto& sq = sh.sq; auto& sc = sh.sc; auto& sidx = sh.sidx; auto& sf = sh.sf;
+  auto& r2d = sh.r2d; auto& rft = sh.rft; auto& rflag = sh.rflag; auto& smax = sh.smax;
 
-  __shared__ float4 sg[BATCH];     // u, v (tile-local), opacity, log2 threshold
-  __shared__ float4 sq[BATCH];     // scaled conic (as in the forward)
-  __shared__ float4 sc[BATCH];     // unscaled conic A, B, C
-  __shared__ int32_t sidx[BATCH];
-  __shared__ __align__(16) float sf[BATCH][C + 4];
-  __shared__ float r2d[4][BATCH][8];
-  __shared__ float rft[4][BATCH][C];
-  __shared__ int32_t rflag[4][BATCH];
-  __shared__ int32_t smax;
-
-  const size_t HW = (size_t)a.W * a.H;
-  const size_t pix = inside ? (size_t)py * a.W + px : 0;
+  const size_t HW = (size_t)W * H;
+  const size_t pix = inside ? (size_t)py * W + px : 0;
   float g[C];
   float T = 1.f, gA = 0.f, sgS = 0.f, Tfin = 1.f;
   int last = -1;
   if (inside) {
-    Tfin = a.T_final[pix];
+    Tfin = q.T_final[pix];
     T = Tfin;
-    last = a.last[pix];
-    gA = a.d_alpha ? a.d_alpha[pix] : 0.f;
+    last = q.last[pix];
+    gA = q.d_alpha ? q.d_alpha[pix] : 0.f;
     float gb = 0.f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      g[c] = a.d_img[c * HW + pix];
-      gb = __builtin_fmaf(g[c], a.bg ? a.bg[c] : 0.f, gb);
+      g[c] = q.d_img[c * HW + pix];
+      gb = __builtin_fmaf(g[c], q.bg ? q.bg[c] : 0.f, gb);
     }
     sgS = Tfin * gb;
   } else {
@@ -119,7 +123,10 @@ __global__ void __launch_bounds__(256) k_render_bwd(BackwardArgs a) {
   if (last >= 0) atomicMax(&smax, last);
   __syncthreads();
   const int maxlast = smax;
-  if (maxlast < 0) return;
+  if (maxlast < 0) {
+    __syncthreads();                 // smax is rewritten by the next tile
+    return;
+  }
   const float gAT = gA * Tfin;
 
   for (int b = maxlast / BATCH; b >= 0; --b) {
@@ -135,7 +142,7 @@ __global__ void __launch_bounds__(256) k_render_bwd(BackwardArgs a) {
       sq[tid] = make_float4(-0.5f * LOG2E * co.x, -LOG2E * co.y, -0.5f * LOG2E * co.z, 0.f);
       sc[tid] = make_float4(co.x, co.y, co.z, 0.f);
       sidx[tid] = gi;
-      const float4* fr = reinterpret_cast<const float4*>(a.feat + (size_t)gi * C);
+      const float4* fr = reinterpret_cast<const float4*>(q.feat + (size_t)(gi - q.g_off) * C);
 #pragma unroll
       for (int q = 0; q < C / 4; ++q) *reinterpret_cast<float4*>(&sf[tid][4 * q]) = fr[q];
     }
@@ -204,8 +211,8 @@ __global__ void __launch_bounds__(256) k_render_bwd(BackwardArgs a) {
       }
       if (any) {
         const int gi = sidx[j];
-        if (v < 6) atomicAdd(&a.g2d[(int64_t)v * a.n + gi], sum);
-        else atomicAdd(&a.g_feat[(size_t)gi * C + (v - 6)], sum);
+        if (v < 6) atomicAdd(&a.g2d[(int64_t)v * a.g_cap + gi], sum);
+        else atomicAdd(&q.d_feat[(size_t)(gi - q.g_off) * C + (v - 6)], sum);
       }
     }
     __syncthreads();
@@ -214,32 +221,78 @@ __global__ void __launch_bounds__(256) k_render_bwd(BackwardArgs a) {
   }
 }
 
+template <int C, int BATCH>
+__global__ void __launch_bounds__(256) k_render_bwd(BatchArgs a) {
+  if (a.dev->overflow) return;
+  const BatchHdr h = batch_hdr(a);
+  __shared__ BwdShared<C, BATCH> sh;
+  __shared__ int s_tile;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(&a.dev->bwd_queue, 1);
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();
+    const int r = req_of_tile(a, h, t);
+    if (r < 0) break;
+    const ReqDev& q = batch_req(a, r);
+    const int lt = t - q.tile_off;
+    bwd_tile<C, BATCH>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, sh);
+  }
+  if (tid == 0 && atomicAdd(&a.dev->bwd_done, 1) == (int)gridDim.x - 1) {
+    atomicExch(&a.dev->bwd_queue, 0);
+    atomicExch(&a.dev->bwd_done, 0);
+  }
+}
+
+// zero the 2D accumulators of the batch and each request's feature gradient
+__global__ void k_bwd_zero(BatchArgs a, int c) {
+  const BatchHdr h = batch_hdr(a);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < 6 * a.g_cap; i += stride) a.g2d[i] = 0.f;
+  for (int r = 0; r < h.n_req; ++r) {
+    const ReqDev& q = batch_req(a, r);
+    for (int64_t i = i0; i < q.n * c; i += stride) q.d_feat[i] = 0.f;
+  }
+}
+
+constexpr int BWD_PERSISTENT_WG = 256 * 6;
+
 template <int C>
-hipError_t launch_bwd_c(const BackwardArgs& a, hipStream_t s) {
+hipError_t launch_bwd_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s) {
   constexpr int BATCH = 32;
-  hipLaunchKernelGGL((k_render_bwd<C, BATCH>), dim3(a.n_tiles), dim3(256), 0, s, a);
+  const int grid = grid_tiles < BWD_PERSISTENT_WG ? (grid_tiles > 0 ? grid_tiles : 1) : BWD_PERSISTENT_WG;
+  hipLaunchKernelGGL((k_render_bwd<C, BATCH>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------- project backward
-__global__ void __launch_bounds__(256) k_project_bwd(ProjectBwdArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
-  const int64_t n = a.n;
+__global__ void __launch_bounds__(256) k_project_bwd(BatchArgs a) {
+  const BatchHdr h = batch_hdr(a);
+  const int64_t g0 = (int64_t)blockIdx.x * 256;
+  const int rq = req_of_gauss(a, h, g0);
+  if (rq < 0) return;
+  const ReqDev& qr = batch_req(a, rq);
+  const int64_t gi = g0 + threadIdx.x;
+  const int64_t i = gi - qr.g_off;
+  const int64_t n = qr.n;
+  if (i >= n) return;
+  const int64_t gc = a.g_cap;
   double dmu[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dlg = 0;
-  const uint2 r = a.rect[i];
+  const uint2 r = a.rect[gi];
   const bool live = (r.x & 0xffffu) <= (r.x >> 16);
   if (live) {
-    const CamArgs& c = a.cam;
+    const CamArgs& c = qr.cam;
     double W[9];
     for (int k = 0; k < 9; ++k) W[k] = c.R[k];
-    const double X = a.mean[i], Y = a.mean[n + i], Z = a.mean[2 * n + i];
+    const double X = qr.mean[i], Y = qr.mean[n + i], Z = qr.mean[2 * n + i];
     const double tx = W[0] * X + W[1] * Y + W[2] * Z + (double)c.t[0];
     const double ty = W[3] * X + W[4] * Y + W[5] * Z + (double)c.t[1];
     const double tz = W[6] * X + W[7] * Y + W[8] * Z + (double)c.t[2];
     const double fx = c.fx, fy = c.fy;
-    const double s3[3] = {a.scale[i], a.scale[n + i], a.scale[2 * n + i]};
-    const double q0[4] = {a.quat[i], a.quat[n + i], a.quat[2 * n + i], a.quat[3 * n + i]};
+    const double s3[3] = {qr.scale[i], qr.scale[n + i], qr.scale[2 * n + i]};
+    const double q0[4] = {qr.quat[i], qr.quat[n + i], qr.quat[2 * n + i], qr.quat[3 * n + i]};
     const double nq = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
     const double qw = q0[0] / nq, qx = q0[1] / nq, qy = q0[2] / nq, qz = q0[3] / nq;
     const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
@@ -265,9 +318,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(ProjectBwdArgs a) {
     const double sc = AS[3] * A[3] + AS[4] * A[4] + AS[5] * A[5] + 0.3;
     const double det = sa * sc - sb * sb;
     const double cA = sc / det, cB = -sb / det, cC = sa / det;
-    const double gu = a.g2d[i], gv = a.g2d[n + i];
-    const double gA = a.g2d[2 * n + i], gB = a.g2d[3 * n + i], gC = a.g2d[4 * n + i];
-    const double gO = a.g2d[5 * n + i];
+    const double gu = a.g2d[gi], gv = a.g2d[gc + gi];
+    const double gA = a.g2d[2 * gc + gi], gB = a.g2d[3 * gc + gi], gC = a.g2d[4 * gc + gi];
+    const double gO = a.g2d[5 * gc + gi];
     // conic = inverse(Sigma'): G_Sigma = -Q G_Q Q with G_Q = [[gA, gB/2], [gB/2, gC]]
     const double Q[4] = {cA, cB, cB, cC};
     const double GQ[4] = {gA, 0.5 * gB, 0.5 * gB, gC};
@@ -327,32 +380,34 @@ __global__ void __launch_bounds__(256) k_project_bwd(ProjectBwdArgs a) {
     const double dot = qw * gq[0] + qx * gq[1] + qy * gq[2] + qz * gq[3];
     const double qh[4] = {qw, qx, qy, qz};
     for (int k = 0; k < 4; ++k) dq[k] = (gq[k] - qh[k] * dot) / nq;
-    const double o = a.opacity[i];
+    const double o = qr.opacity[i];
     dlg = o * (1.0 - o) * gO;
   }
-  if (a.d_mean)
-    for (int k = 0; k < 3; ++k) a.d_mean[k * n + i] = (float)dmu[k];
-  if (a.d_log_scale)
-    for (int k = 0; k < 3; ++k) a.d_log_scale[k * n + i] = (float)dls[k];
-  if (a.d_quat)
-    for (int k = 0; k < 4; ++k) a.d_quat[k * n + i] = (float)dq[k];
-  if (a.d_logit) a.d_logit[i] = (float)dlg;
+  if (qr.d_mean)
+    for (int k = 0; k < 3; ++k) qr.d_mean[k * n + i] = (float)dmu[k];
+  if (qr.d_log_scale)
+    for (int k = 0; k < 3; ++k) qr.d_log_scale[k * n + i] = (float)dls[k];
+  if (qr.d_quat)
+    for (int k = 0; k < 4; ++k) qr.d_quat[k * n + i] = (float)dq[k];
+  if (qr.d_logit) qr.d_logit[i] = (float)dlg;
 }
 
 }  // namespace
 
-hipError_t launch_render_bwd(const BackwardArgs& a, int c, hipStream_t s) {
+hipError_t launch_render_bwd(const BatchArgs& a, int c, int64_t grid_gauss, int32_t grid_tiles,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_bwd_zero, dim3(1024), dim3(256), 0, s, a, c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   switch (c) {
-    case 8: return launch_bwd_c<8>(a, s);
-    case 16: return launch_bwd_c<16>(a, s);
-    case 32: return launch_bwd_c<32>(a, s);
-    case 64: return launch_bwd_c<64>(a, s);
+    case 8: e = launch_bwd_c<8>(a, grid_tiles, s); break;
+    case 16: e = launch_bwd_c<16>(a, grid_tiles, s); break;
+    case 32: e = launch_bwd_c<32>(a, grid_tiles, s); break;
+    case 64: e = launch_bwd_c<64>(a, grid_tiles, s); break;
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.n + 255) / 256;
+  if (e != hipSuccess) return e;
+  const int64_t blocks = (grid_gauss + 255) / 256;
   hipLaunchKernelGGL(k_project_bwd, dim3((int)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, a);
   return hipGetLastError();
 }

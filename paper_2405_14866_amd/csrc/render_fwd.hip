@@ -1,8 +1,9 @@
 // render_fwd.hip -- step 3 of the rasterizer: per-tile front-to-back blend
 // of C-channel latent features (gfx950).
 //
-// One 256-lane workgroup (4 wave64) per 16x16 tile, one pixel per lane; wave
-// w owns the 8x8 quadrant (w & 1, w >> 1) of the tile.  The tile's sorted
+// Persistent workgroups of 256 lanes (4 wave64) take tiles of the batch's
+// global tile space from a device work queue; one pixel per lane, wave w
+// owns the 8x8 quadrant (w & 1, w >> 1) of the tile.  The tile's sorted
 // Gaussian list is consumed in batches of B entries, double-buffered in LDS:
 //   * while batch b is blended, batch b+1 is fetched: its feature rows go
 //     straight from HBM into LDS with global_load_lds_dwordx4 (no VGPRs, no
@@ -21,11 +22,21 @@
 //     ballot mask), so Gaussians that only touch the other quadrants cost
 //     it nothing;
 //   * the per-Gaussian body has a single wave-uniform branch for the
-//     exponential and one for the C-channel FMAs; the rest are selects.
+//     exponential and one for the feature accumulation; the rest are
+//     selects;
+//   * the feature accumulation of a step is the rank-1 update F += w f^T of
+//     the wave's 64 pixels x C channels (w: each lane's blend weight, 0 where
+//     it does not blend).  It runs on the matrix cores as C/4
+//     v_mfma_f32_4x4x1_16b_f32: block b of lanes 4b..4b+3 (four consecutive
+//     pixels of a row) takes the lanes' own weights as A, and instruction m
+//     covers channels m + (C/4) q, q = lane & 3, so each lane's B operands
+//     are one contiguous C/4-float slice of the feature row (C/16
+//     ds_read_b128 per lane instead of C/4 full-row broadcasts).  This moves
+//     the C FMAs per step off the VALU and cuts the LDS bytes of a step
+//     four-fold; the background enters as one last update with weight T.
 // Per pixel: P = -d^T conic d / 2; skip when P > 0 or when P is below the
 // opacity threshold (alpha < 1/255); alpha = min(0.99, o e^P); a Gaussian
 // that would take T below 1e-4 ends the pixel without being blended.
-// Features accumulate in registers (C VGPRs per lane).
 #include "tg_internal.h"
 
 namespace tg {
@@ -33,23 +44,42 @@ namespace {
 
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float CULL_MARGIN = 0.0625f;   // px added to the alpha-support box
+constexpr int RENDER_B = 64;             // Gaussians per staged batch
+constexpr int PERSISTENT_WG = 256 * 8;   // persistent workgroups (>= resident capacity)
 
 typedef __attribute__((address_space(3))) void lds_void;
+typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Gather feature rows [r0, r0 + B) of the list into LDS (row-major, C
-// floats each) with one 16-byte LDS-DMA load per lane per instruction.
+// Gather feature rows [0, nb) of the batch (global indices in sidx) into
+// LDS (row-major, C floats each) with one 16-byte LDS-DMA load per lane per
+// instruction.
 template <int C, int B>
-__device__ __forceinline__ void dma_features(const float* __restrict__ feat, const int32_t* sidx,
-                                             float* dst, int nb, int w, int lane) {
+__device__ __forceinline__ void dma_features(const float* __restrict__ feat, int64_t g_off,
+                                             const int32_t* sidx, float* dst, int nb, int w, int lane) {
   constexpr int CHUNKS = C / 4;              // 16-byte chunks per row
   constexpr int INSTR = B * CHUNKS / 64;     // wave-wide loads per batch
 #pragma unroll
   for (int k = w; k < INSTR; k += 4) {
     const int q = k * 64 + lane;
     const int r = q / CHUNKS, p = q % CHUNKS;
-    const int g = sidx[r < nb ? r : 0];
-    const float* src = feat + (size_t)g * C + 4 * p;
+    const int64_t g = (int64_t)sidx[r < nb ? r : 0] - g_off;
+    const float* src = feat + g * C + 4 * p;
     __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(dst + k * 256), 16, 0, 0);
+  }
+}
+
+// this lane's C/4 contiguous features of a row (LDS), for the MFMA B operands
+template <int NM>
+__device__ __forceinline__ void load_slice(const float* p, float (&fl)[NM]) {
+  if constexpr (NM % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < NM / 4; ++k) {
+      const float4 v = reinterpret_cast<const float4*>(p)[k];
+      fl[4 * k] = v.x; fl[4 * k + 1] = v.y; fl[4 * k + 2] = v.z; fl[4 * k + 3] = v.w;
+    }
+  } else {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    fl[0] = v.x; fl[1] = v.y;
   }
 }
 
@@ -78,52 +108,61 @@ __device__ __forceinline__ void make_state(double2 xy, float4 co, double ox, dou
   cq = make_float4(-0.5f * LOG2E * co.x, -LOG2E * co.y, -0.5f * LOG2E * co.z, __uint_as_float(mask));
 }
 
+struct WorkCount {
+  uint32_t n_eval = 0, n_blend = 0, steps = 0, steps_pass = 0, steps_blend = 0;
+};
+
+template <int C, int B>
+struct RenderShared {
+  float4 st[2][B];
+  float4 cq[2][B];
+  int32_t sidx[2][B];
+  __align__(16) float fe[2][B * C];
+};
+
+// Blend one tile (tile-local coordinates tx, ty of request q).
 template <int C, int B, bool COUNT>
-__global__ void __launch_bounds__(256) k_render(RenderArgs a) {
-  static_assert(B % 64 == 0 && (B * C / 4) % 64 == 0, "batch shape");
-  if (a.dev->overflow) return;
-  const int tile = blockIdx.x;
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+__device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q, int gtile, int tx,
+                                            int ty, RenderShared<C, B>& sh, WorkCount& wc) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int W = q.cam.W, H = q.cam.H;
   const int lx = ((w & 1) << 3) | (lane & 7);
   const int ly = ((w >> 1) << 3) | (lane >> 3);
   const int px = tx * TILE + lx, py = ty * TILE + ly;
-  const bool inside = px < a.W && py < a.H;
+  const bool inside = px < W && py < H;
   const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
   const double ox = (double)(tx * TILE), oy = (double)(ty * TILE);
-  const int s = a.tile_start[tile], e = a.tile_start[tile + 1];
+  const int s = a.tile_start[gtile], e = a.tile_start[gtile + 1];
   const int len = e - s;
   const uint32_t qbit = 1u << w;
+  const float* feat = q.feat;
+  const int64_t g_off = q.g_off;
 
-  __shared__ float4 st[2][B];
-  __shared__ float4 cq[2][B];
-  __shared__ int32_t sidx[2][B];
-  __shared__ __align__(16) float fe[2][B * C];
-
-  float acc[C];
+  constexpr int NM = C / 4;           // MFMA updates per blend step
+  const int q4 = lane & 3;
+  f4v acc[NM];                        // acc[m][r]: channel m + NM q4, pixel (lane & ~3) + r
 #pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = 0.f;
+  for (int m = 0; m < NM; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
   float T = 1.f;
   int last = -1;
   bool done = !inside;
   int stop_pos = -1;                  // list position that ended the pixel (COUNT only)
-  uint32_t n_blend = 0, steps = 0, steps_pass = 0, steps_blend = 0;
 
   const int nbatch = (len + B - 1) / B;
   // prologue: indices of batches 0 and 1, then batch 0 staged
   if (tid < B) {
-    sidx[0][tid] = tid < len ? a.sorted[s + tid] : 0;
-    sidx[1][tid] = B + tid < len ? a.sorted[s + B + tid] : 0;
+    sh.sidx[0][tid] = tid < len ? a.sorted[s + tid] : 0;
+    sh.sidx[1][tid] = B + tid < len ? a.sorted[s + B + tid] : 0;
   }
   __syncthreads();
   if (nbatch > 0) {
-    dma_features<C, B>(a.feat, sidx[0], fe[0], min(B, len), w, lane);
+    dma_features<C, B>(feat, g_off, sh.sidx[0], sh.fe[0], min(B, len), w, lane);
     if (tid < B && tid < len) {
-      const int g = sidx[0][tid];
+      const int g = sh.sidx[0][tid];
       float4 s0, s1;
       make_state(a.xy[g], a.conic_o[g], ox, oy, s0, s1);
-      st[0][tid] = s0;
-      cq[0][tid] = s1;
+      sh.st[0][tid] = s0;
+      sh.cq[0][tid] = s1;
     }
     __builtin_amdgcn_s_waitcnt(0);
   }
@@ -140,18 +179,18 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a) {
     float4 pco = make_float4(0.f, 0.f, 0.f, 0.f);
     int pidx = 0;
     if (more) {
-      dma_features<C, B>(a.feat, sidx[nxt], fe[nxt], nb1, w, lane);
+      dma_features<C, B>(feat, g_off, sh.sidx[nxt], sh.fe[nxt], nb1, w, lane);
       if (tid < nb1) {
-        const int g = sidx[nxt][tid];
+        const int g = sh.sidx[nxt][tid];
         pxy = a.xy[g];
         pco = a.conic_o[g];
       }
       if (tid < B && b0 + 2 * B + tid < len) pidx = a.sorted[s + b0 + 2 * B + tid];
     }
     // ---- blend batch b: walk the Gaussians that reach this wave's quadrant
-    const float4* stc = st[cur];
-    const float4* cqc = cq[cur];
-    const float* fec = fe[cur];
+    const float4* stc = sh.st[cur];
+    const float4* cqc = sh.cq[cur];
+    const float* fec = sh.fe[cur];
     for (int m0 = 0; m0 < nb; m0 += 64) {
       const int jj = m0 + lane;
       const bool reach = jj < nb && (__float_as_uint(cqc[jj].w) & qbit) != 0;
@@ -161,13 +200,13 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a) {
         const int j = m0 + (int)__builtin_ctzll(mask);
         mask &= mask - 1;
         const float4 gs = stc[j];
-        const float4 q = cqc[j];
+        const float4 qv = cqc[j];
         const float dx = fpx - gs.x, dy = fpy - gs.y;
-        const float P = __builtin_fmaf(dx, __builtin_fmaf(q.x, dx, q.y * dy), q.z * dy * dy);
+        const float P = __builtin_fmaf(dx, __builtin_fmaf(qv.x, dx, qv.y * dy), qv.z * dy * dy);
         const bool pass = !done && P <= 0.f && P >= gs.w;
-        if (COUNT) ++steps;
+        if (COUNT) ++wc.steps;
         if (__ballot(pass) == 0) continue;
-        if (COUNT) ++steps_pass;
+        if (COUNT) ++wc.steps_pass;
         const float al = fminf(0.99f, gs.z * __builtin_amdgcn_exp2f(P));
         const bool ok = pass && al >= 1.f / 255.f;
         const float Tn = T * (1.f - al);
@@ -178,12 +217,13 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a) {
         const float wgt = blend ? al * T : 0.f;
         T = blend ? Tn : T;
         last = blend ? b0 + j : last;
-        if (COUNT && blend) ++n_blend;
+        if (COUNT && blend) ++wc.n_blend;
         if (__ballot(blend) != 0) {
-          if (COUNT) ++steps_blend;
-          const float* f = fec + j * C;
+          if (COUNT) ++wc.steps_blend;
+          float fl[NM];
+          load_slice<NM>(fec + j * C + NM * q4, fl);
 #pragma unroll
-          for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(wgt, f[c], acc[c]);
+          for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt, fl[m], acc[m], 0, 0, 0);
         }
       }
     }
@@ -192,35 +232,86 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a) {
       if (tid < nb1) {
         float4 s0, s1;
         make_state(pxy, pco, ox, oy, s0, s1);
-        st[nxt][tid] = s0;
-        cq[nxt][tid] = s1;
+        sh.st[nxt][tid] = s0;
+        sh.cq[nxt][tid] = s1;
       }
-      if (tid < B) sidx[cur][tid] = pidx;
+      if (tid < B) sh.sidx[cur][tid] = pidx;
     }
     __builtin_amdgcn_s_waitcnt(0);
     if (__syncthreads_count(!done) == 0) break;
   }
-  if (inside) {
-    const size_t HW = (size_t)a.W * a.H;
-    const size_t pix = (size_t)py * a.W + px;
+  if (q.bg) {                         // F += T_final bg, as one more rank-1 update
+    float bl[NM];
 #pragma unroll
-    for (int c = 0; c < C; ++c) a.out_feat[c * HW + pix] = acc[c] + T * (a.bg ? a.bg[c] : 0.f);
-    if (a.out_alpha) a.out_alpha[pix] = 1.f - T;
-    a.T_final[pix] = T;
-    a.last[pix] = last;
+    for (int m = 0; m < NM; ++m) bl[m] = q.bg[m + NM * q4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(T, bl[m], acc[m], 0, 0, 0);
+  }
+  if (inside) {
+    const size_t pix = (size_t)py * W + px;
+    if (q.out_alpha) q.out_alpha[pix] = 1.f - T;
+    q.T_final[pix] = T;
+    q.last[pix] = last;
+  }
+  {
+    // lane 4b + q4 holds channels m + NM q4 of the four pixels of block b,
+    // which are consecutive in one row of the quadrant
+    const size_t HW = (size_t)W * H;
+    const int b4 = lane & ~3;
+    const int px0 = tx * TILE + ((w & 1) << 3) + (b4 & 7);
+    const int py0 = ty * TILE + ((w >> 1) << 3) + (b4 >> 3);
+    if (py0 < H) {
+      float* base = q.out_feat + (size_t)py0 * W + px0;
+      if (px0 + 3 < W && (W & 3) == 0) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+          *reinterpret_cast<float4*>(base + (size_t)(m + NM * q4) * HW) =
+              make_float4(acc[m][0], acc[m][1], acc[m][2], acc[m][3]);
+      } else {
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (px0 + r < W) base[(size_t)(m + NM * q4) * HW + r] = acc[m][r];
+      }
+    }
+  }
+  if (COUNT && inside) {
+    // evaluated pairs of the plain walk: every list position up to the stop
+    wc.n_eval += stop_pos >= 0 ? (uint32_t)(stop_pos + 1) : (uint32_t)len;
+  }
+  __syncthreads();                    // LDS buffers are reused by the next tile
+}
+
+template <int C, int B, bool COUNT>
+__global__ void __launch_bounds__(256) k_render(BatchArgs a) {
+  if (a.dev->overflow) return;
+  const BatchHdr h = batch_hdr(a);
+  __shared__ RenderShared<C, B> sh;
+  __shared__ int s_tile;
+  const int tid = threadIdx.x;
+  WorkCount wc;
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(&a.dev->tile_queue, 1);
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();
+    const int r = req_of_tile(a, h, t);
+    if (r < 0) break;
+    const ReqDev& q = batch_req(a, r);
+    const int lt = t - q.tile_off;
+    render_tile<C, B, COUNT>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, sh, wc);
   }
   if (COUNT) {
-    // evaluated pairs of the plain walk: every list position up to the stop
-    const uint32_t n_eval = !inside ? 0u : (stop_pos >= 0 ? (uint32_t)(stop_pos + 1) : (uint32_t)len);
     __shared__ unsigned long long cnt[5];
     if (tid < 5) cnt[tid] = 0;
     __syncthreads();
-    atomicAdd(&cnt[0], (unsigned long long)n_eval);
-    atomicAdd(&cnt[1], (unsigned long long)n_blend);
-    if (lane == 0) {
-      atomicAdd(&cnt[2], (unsigned long long)steps);
-      atomicAdd(&cnt[3], (unsigned long long)steps_pass);
-      atomicAdd(&cnt[4], (unsigned long long)steps_blend);
+    atomicAdd(&cnt[0], (unsigned long long)wc.n_eval);
+    atomicAdd(&cnt[1], (unsigned long long)wc.n_blend);
+    if ((tid & 63) == 0) {
+      atomicAdd(&cnt[2], (unsigned long long)wc.steps);
+      atomicAdd(&cnt[3], (unsigned long long)wc.steps_pass);
+      atomicAdd(&cnt[4], (unsigned long long)wc.steps_blend);
     }
     __syncthreads();
     if (tid == 0) {
@@ -230,6 +321,11 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs a) {
       atomicAdd(&a.dev->wave_pass, cnt[3]);
       atomicAdd(&a.dev->wave_blend, cnt[4]);
     }
+  }
+  // the last workgroup out re-arms the queue for the next launch
+  if (tid == 0 && atomicAdd(&a.dev->tile_done, 1) == (int)gridDim.x - 1) {
+    atomicExch(&a.dev->tile_queue, 0);
+    atomicExch(&a.dev->tile_done, 0);
   }
 }
 
@@ -242,13 +338,13 @@ __global__ void k_zero_work(FrameDev* d) {
 }
 
 template <int C>
-hipError_t launch_c(const RenderArgs& a, hipStream_t s, bool count) {
-  constexpr int B = 64;
+hipError_t launch_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s, bool count) {
+  const int grid = grid_tiles < PERSISTENT_WG ? (grid_tiles > 0 ? grid_tiles : 1) : PERSISTENT_WG;
   if (count) {
     hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(1), 0, s, a.dev);
-    hipLaunchKernelGGL((k_render<C, B, true>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_render<C, RENDER_B, true>), dim3(grid), dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_render<C, B, false>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_render<C, RENDER_B, false>), dim3(grid), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -261,12 +357,13 @@ __global__ void k_fill_zero(float* p, int64_t n) {
 
 }  // namespace
 
-hipError_t launch_render_fwd(const RenderArgs& a, int c, hipStream_t s, bool count_work) {
+hipError_t launch_render_fwd(const BatchArgs& a, int c, int32_t grid_tiles, hipStream_t s,
+                             bool count_work) {
   switch (c) {
-    case 8: return launch_c<8>(a, s, count_work);
-    case 16: return launch_c<16>(a, s, count_work);
-    case 32: return launch_c<32>(a, s, count_work);
-    case 64: return launch_c<64>(a, s, count_work);
+    case 8: return launch_c<8>(a, grid_tiles, s, count_work);
+    case 16: return launch_c<16>(a, grid_tiles, s, count_work);
+    case 32: return launch_c<32>(a, grid_tiles, s, count_work);
+    case 64: return launch_c<64>(a, grid_tiles, s, count_work);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,530 @@
+// serve.hip -- the batched serving loop of include/tg.h (tg_serve_*).
+//
+// Continuous batching of render requests on one GPU:
+//   * clients submit requests from any thread (a ticket per request); each
+//     points at Gaussian buffers that stay resident on the device;
+//   * a scheduler thread admits queued requests first in, first out while
+//     the bytes of the requests in flight (workspace share + outputs) plus
+//     the streams' resident arenas stay within the budget, and while the
+//     slot's capacities (Gaussians, keys, tiles, pixels) hold;
+//   * whenever a slot is free it forms a batch of everything admissible (up
+//     to max_batch requests) and launches it: the request table goes to
+//     the device by one pinned copy, then one launch per step (projection,
+//     binning, sort, blend) covers every request of the batch - the kernels
+//     read the table, their grids are the slot's capacity and the blend is a
+//     persistent work-queue kernel over the batch's tiles.  With use_graph
+//     that whole sequence is a HIP graph captured once per slot and
+//     replayed per batch;
+//   * slots run on separate streams, so a batch formed while others are on
+//     the GPU overlaps with them on the device;
+//   * a batch whose keys overflow the slot is re-admitted request by request
+//     (a request that overflows alone fails with TG_ERR_CAPACITY).
+// Latency of a request = completion observed by the scheduler - submit.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tg.h"
+#include "tg_internal.h"
+
+namespace tg {
+int ctx_device(const tg_ctx* c);
+}
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Ticket {
+  tg_request req{};
+  int32_t status = TG_PENDING;
+  int32_t batch_size = 0, slot = -1, retries = 0;
+  bool solo = false;             // re-admitted after an overflow: run alone
+  int64_t footprint = 0;
+  int64_t t_submit = 0, t_launch = 0, t_done = 0;
+};
+
+struct Arena {
+  float* mean = nullptr;
+  float* scale = nullptr;
+  float* quat = nullptr;
+  float* opacity = nullptr;
+  float* feat = nullptr;
+  int64_t max_n = 0;
+  int64_t bytes = 0;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  // workspace
+  double2* xy = nullptr;
+  float4* conic_o = nullptr;
+  uint2* rect = nullptr;
+  uint32_t* depth = nullptr;
+  int32_t* tile_count = nullptr;
+  int32_t* tile_start = nullptr;
+  int32_t* tile_cursor = nullptr;
+  uint64_t* keys = nullptr;
+  uint64_t* keys_tmp = nullptr;
+  int32_t* sorted = nullptr;
+  float* T_final = nullptr;
+  int32_t* last = nullptr;
+  float* g2d = nullptr;
+  tg::FrameDev* dev = nullptr;
+  tg::ReqDev* table_dev = nullptr;
+  tg::BatchHdr* hdr_dev = nullptr;
+  // pinned host mirrors
+  tg::ReqDev* table_host = nullptr;
+  tg::BatchHdr* hdr_host = nullptr;
+  tg::FrameDev* dev_host = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool busy = false;
+  std::vector<uint64_t> tickets;
+};
+
+template <class T>
+bool dalloc(T** p, size_t count) {
+  *p = nullptr;
+  return hipMalloc(reinterpret_cast<void**>(p), (count ? count : 1) * sizeof(T)) == hipSuccess;
+}
+template <class T>
+bool halloc(T** p, size_t count) {
+  *p = nullptr;
+  return hipHostMalloc(reinterpret_cast<void**>(p), (count ? count : 1) * sizeof(T), 0) == hipSuccess;
+}
+
+}  // namespace
+
+struct tg_server {
+  tg_ctx* ctx = nullptr;
+  int device = 0;
+  tg_serve_opts opts{};
+  int64_t cap_gauss = 0, cap_keys = 0, cap_pixels = 0;
+  int32_t cap_tiles = 0, max_tiles_req = 0;
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv;        // wakes the scheduler
+  std::condition_variable done_cv;   // wakes tg_serve_wait
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, Ticket> tickets;
+  std::unordered_map<int32_t, Arena> arenas;
+  uint64_t next_ticket = 1;
+  int64_t budget_used = 0;
+  bool stop = false;
+  std::thread sched;
+  bool failed = false;               // a HIP error stopped the scheduler
+};
+
+namespace {
+
+int32_t tiles_of(const tg_camera& c) {
+  return ((c.width + tg::TILE - 1) / tg::TILE) * ((c.height + tg::TILE - 1) / tg::TILE);
+}
+
+int64_t keys_est(const tg_server* s, int64_t n) {
+  return (int64_t)((double)n * s->opts.keys_per_gaussian) + 1024;
+}
+
+// device bytes a request occupies while in flight: its share of the slot
+// workspace and its outputs
+int64_t footprint_of(const tg_server* s, const tg_request& r) {
+  const int64_t px = (int64_t)r.cam.width * r.cam.height;
+  return tg::padded(r.g.n) * 44 + keys_est(s, r.g.n) * 20 + px * (8 + 4 * ((int64_t)s->opts.c + 1));
+}
+
+tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
+  tg::BatchArgs b{};
+  b.table = sl.table_dev;
+  b.hdr_dev = sl.hdr_dev;
+  b.xy = sl.xy;
+  b.conic_o = sl.conic_o;
+  b.rect = sl.rect;
+  b.depth = sl.depth;
+  b.tile_count = sl.tile_count;
+  b.tile_start = sl.tile_start;
+  b.tile_cursor = sl.tile_cursor;
+  b.keys = sl.keys;
+  b.keys_tmp = sl.keys_tmp;
+  b.sorted = sl.sorted;
+  b.g2d = sl.g2d;
+  b.g_cap = s->cap_gauss;
+  b.key_cap = s->cap_keys;
+  b.dev = sl.dev;
+  return b;
+}
+
+// the batch's work on the slot stream: table upload, every step, status download
+hipError_t enqueue_batch(const tg_server* s, const Slot& sl) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(sl.table_dev, sl.table_host, sizeof(tg::ReqDev) * tg::MAX_BATCH,
+                          hipMemcpyHostToDevice, sl.stream)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(sl.hdr_dev, sl.hdr_host, sizeof(tg::BatchHdr), hipMemcpyHostToDevice,
+                          sl.stream)) != hipSuccess)
+    return e;
+  const tg::BatchArgs a = slot_args(s, sl);
+  if ((e = tg::launch_project(a, s->cap_gauss, sl.stream)) != hipSuccess) return e;
+  if ((e = tg::launch_bin_sort(a, s->cap_gauss, s->cap_tiles, s->max_tiles_req, sl.stream)) != hipSuccess)
+    return e;
+  if ((e = tg::launch_render_fwd(a, s->opts.c, s->cap_tiles, sl.stream)) != hipSuccess) return e;
+  return hipMemcpyAsync(sl.dev_host, sl.dev, sizeof(tg::FrameDev), hipMemcpyDeviceToHost, sl.stream);
+}
+
+void free_slot(Slot& sl) {
+  if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+  if (sl.graph) (void)hipGraphDestroy(sl.graph);
+  void* d[] = {sl.xy, sl.conic_o, sl.rect, sl.depth, sl.tile_count, sl.tile_start, sl.tile_cursor,
+               sl.keys, sl.keys_tmp, sl.sorted, sl.T_final, sl.last, sl.g2d, sl.dev, sl.table_dev,
+               sl.hdr_dev};
+  for (void* p : d)
+    if (p) (void)hipFree(p);
+  void* h[] = {sl.table_host, sl.hdr_host, sl.dev_host};
+  for (void* p : h)
+    if (p) (void)hipHostFree(p);
+  if (sl.done) (void)hipEventDestroy(sl.done);
+  if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  sl = Slot{};
+}
+
+bool alloc_slot(tg_server* s, Slot& sl) {
+  const size_t g = (size_t)s->cap_gauss, k = (size_t)s->cap_keys, t = (size_t)s->cap_tiles,
+               px = (size_t)s->cap_pixels;
+  bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+            dalloc(&sl.xy, g) && dalloc(&sl.conic_o, g) && dalloc(&sl.rect, g) && dalloc(&sl.depth, g) &&
+            dalloc(&sl.tile_count, t) && dalloc(&sl.tile_start, t + 1) && dalloc(&sl.tile_cursor, t) &&
+            dalloc(&sl.keys, k) && dalloc(&sl.keys_tmp, k) && dalloc(&sl.sorted, k) &&
+            dalloc(&sl.T_final, px) && dalloc(&sl.last, px) && dalloc(&sl.g2d, 1) && dalloc(&sl.dev, 1) &&
+            dalloc(&sl.table_dev, tg::MAX_BATCH) && dalloc(&sl.hdr_dev, 1) &&
+            halloc(&sl.table_host, tg::MAX_BATCH) && halloc(&sl.hdr_host, 1) && halloc(&sl.dev_host, 1);
+  if (!ok) return false;
+  ok = hipMemset(sl.dev, 0, sizeof(tg::FrameDev)) == hipSuccess &&
+       hipMemset(sl.table_dev, 0, sizeof(tg::ReqDev) * tg::MAX_BATCH) == hipSuccess &&
+       hipMemset(sl.hdr_dev, 0, sizeof(tg::BatchHdr)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) return false;
+  std::fill_n(reinterpret_cast<char*>(sl.table_host), sizeof(tg::ReqDev) * tg::MAX_BATCH, 0);
+  *sl.hdr_host = tg::BatchHdr{0, 0, 0};
+  if (s->opts.use_graph) {
+    // capture the batch sequence once; replays read the table the first node uploads
+    if (hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    const hipError_t e = enqueue_batch(s, sl);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(sl.stream, &gr);
+    if (e != hipSuccess || e2 != hipSuccess || !gr) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return false;
+    }
+    sl.graph = gr;
+    if (hipGraphInstantiate(&sl.exec, gr, nullptr, nullptr, 0) != hipSuccess) return false;
+  }
+  return true;
+}
+
+// Form and launch one batch on a free slot.  Called with the lock held.
+// Returns false if nothing could be admitted.
+bool launch_batch(tg_server* s, int slot_id) {
+  Slot& sl = s->slots[slot_id];
+  std::vector<uint64_t> batch;
+  int64_t sum_g = 0, sum_k = 0, sum_px = 0;
+  int32_t sum_t = 0;
+  while (!s->queue.empty() && (int)batch.size() < s->opts.max_batch) {
+    Ticket& t = s->tickets[s->queue.front()];
+    const int64_t ng = tg::padded(t.req.g.n), nk = keys_est(s, t.req.g.n);
+    const int64_t npx = (int64_t)t.req.cam.width * t.req.cam.height;
+    const int32_t nt = tiles_of(t.req.cam);
+    if (t.solo && !batch.empty()) break;
+    if (sum_g + ng > s->cap_gauss || sum_t + nt > s->cap_tiles || sum_px + npx > s->cap_pixels ||
+        (sum_k + nk > s->cap_keys && !batch.empty()))
+      break;
+    if (s->budget_used + t.footprint > s->opts.budget_bytes) break;
+    s->budget_used += t.footprint;
+    batch.push_back(s->queue.front());
+    s->queue.pop_front();
+    tg::ReqDev& r = sl.table_host[batch.size() - 1];
+    r = tg::ReqDev{};
+    r.mean = t.req.g.mean; r.scale = t.req.g.scale; r.quat = t.req.g.quat;
+    r.opacity = t.req.g.opacity; r.feat = t.req.g.feat;
+    r.bg = t.req.bg; r.out_feat = t.req.out_feat; r.out_alpha = t.req.out_alpha;
+    r.T_final = sl.T_final + sum_px;
+    r.last = sl.last + sum_px;
+    r.n = t.req.g.n;
+    r.g_off = sum_g;
+    r.tile_off = sum_t;
+    tg::CamArgs& c = r.cam;
+    for (int i = 0; i < 9; ++i) c.R[i] = t.req.cam.R[i];
+    for (int i = 0; i < 3; ++i) c.t[i] = t.req.cam.t[i];
+    c.fx = t.req.cam.fx; c.fy = t.req.cam.fy; c.cx = t.req.cam.cx; c.cy = t.req.cam.cy;
+    c.znear = t.req.cam.znear;
+    c.W = t.req.cam.width; c.H = t.req.cam.height;
+    c.tiles_x = (c.W + tg::TILE - 1) / tg::TILE;
+    c.tiles_y = (c.H + tg::TILE - 1) / tg::TILE;
+    sum_g += ng; sum_k += nk; sum_px += npx; sum_t += nt;
+    if (t.solo) break;
+  }
+  if (batch.empty()) return false;
+  *sl.hdr_host = tg::BatchHdr{(int32_t)batch.size(), sum_t, sum_g};
+  const int64_t t0 = now_ns();
+  hipError_t e = hipSuccess;
+  if (s->opts.use_graph) e = hipGraphLaunch(sl.exec, sl.stream);
+  else e = enqueue_batch(s, sl);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+  for (uint64_t id : batch) {
+    Ticket& t = s->tickets[id];
+    t.t_launch = t0;
+    t.slot = slot_id;
+    t.batch_size = (int32_t)batch.size();
+    if (e != hipSuccess) {
+      t.status = TG_ERR_HIP;
+      t.t_done = now_ns();
+      s->budget_used -= t.footprint;
+    }
+  }
+  if (e != hipSuccess) {
+    s->failed = true;
+    s->done_cv.notify_all();
+    return false;
+  }
+  sl.tickets = std::move(batch);
+  sl.busy = true;
+  return true;
+}
+
+// Retire a finished slot.  Called with the lock held.
+void finish_slot(tg_server* s, Slot& sl) {
+  const bool over = sl.dev_host->overflow != 0;
+  const int64_t t1 = now_ns();
+  std::vector<uint64_t> retry;
+  for (uint64_t id : sl.tickets) {
+    Ticket& t = s->tickets[id];
+    s->budget_used -= t.footprint;
+    if (over && sl.tickets.size() > 1) {
+      t.retries += 1;
+      t.solo = true;
+      retry.push_back(id);
+    } else {
+      t.status = over ? TG_ERR_CAPACITY : TG_OK;
+      t.t_done = t1;
+    }
+  }
+  for (auto it = retry.rbegin(); it != retry.rend(); ++it) s->queue.push_front(*it);
+  sl.tickets.clear();
+  sl.busy = false;
+  s->done_cv.notify_all();
+}
+
+void scheduler(tg_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    bool any_busy = false;
+    for (Slot& sl : s->slots) {
+      if (!sl.busy) continue;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipSuccess) finish_slot(s, sl);
+      else if (q == hipErrorNotReady) any_busy = true;
+      else {   // device error: fail the slot's requests
+        for (uint64_t id : sl.tickets) {
+          Ticket& t = s->tickets[id];
+          t.status = TG_ERR_HIP;
+          t.t_done = now_ns();
+          s->budget_used -= t.footprint;
+        }
+        sl.tickets.clear();
+        sl.busy = false;
+        s->failed = true;
+        s->done_cv.notify_all();
+      }
+    }
+    if (!s->stop && !s->failed) {
+      for (size_t i = 0; i < s->slots.size() && !s->queue.empty(); ++i)
+        if (!s->slots[i].busy && launch_batch(s, (int)i)) any_busy = true;
+    }
+    if (s->stop || s->failed) {
+      if (!any_busy) break;
+    }
+    if (any_busy) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    } else {
+      s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    }
+  }
+  // drop whatever is still queued
+  for (uint64_t id : s->queue) {
+    Ticket& t = s->tickets[id];
+    t.status = s->failed ? TG_ERR_HIP : TG_ERR_INVALID;
+    t.t_done = now_ns();
+  }
+  s->queue.clear();
+  s->done_cv.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+tg_status tg_serve_create(tg_ctx* ctx, const tg_serve_opts* opts, tg_server** out) {
+  if (!ctx || !opts || !out) return TG_ERR_INVALID;
+  *out = nullptr;
+  const tg_serve_opts& o = *opts;
+  if (o.slots < 1 || o.slots > 8 || o.max_batch < 1 || o.max_batch > tg::MAX_BATCH ||
+      o.max_gauss_per_batch < 1 || o.max_keys_per_batch < 1 || o.max_keys_per_batch >= ((int64_t)1 << 31) ||
+      o.max_pixels_per_batch < 1 || o.max_side < 1 || o.max_side > 65535 * tg::TILE || o.budget_bytes <= 0 ||
+      !(o.c == 8 || o.c == 16 || o.c == 32 || o.c == 64) || !(o.keys_per_gaussian > 0.f) ||
+      o.max_gauss_per_batch >= ((int64_t)1 << 31))
+    return TG_ERR_INVALID;
+  const int device = tg::ctx_device(ctx);
+  if (hipSetDevice(device) != hipSuccess) return TG_ERR_HIP;
+  tg_server* s = new (std::nothrow) tg_server;
+  if (!s) return TG_ERR_OOM;
+  s->ctx = ctx;
+  s->device = device;
+  s->opts = o;
+  s->cap_gauss = tg::padded(o.max_gauss_per_batch) + (int64_t)o.max_batch * tg::BIN_CHUNK;
+  s->cap_keys = o.max_keys_per_batch;
+  s->cap_pixels = o.max_pixels_per_batch;
+  const int64_t side_tiles = (o.max_side + tg::TILE - 1) / tg::TILE;
+  s->max_tiles_req = (int32_t)std::min<int64_t>(side_tiles * side_tiles, tg::BIN_LDS_MAX_TILES);
+  s->cap_tiles = (int32_t)(o.max_pixels_per_batch / (tg::TILE * tg::TILE) + (int64_t)o.max_batch * (2 * side_tiles + 1));
+  s->slots.resize(o.slots);
+  for (Slot& sl : s->slots) {
+    if (!alloc_slot(s, sl)) {
+      for (Slot& x : s->slots) free_slot(x);
+      delete s;
+      return TG_ERR_OOM;
+    }
+  }
+  s->sched = std::thread(scheduler, s);
+  *out = s;
+  return TG_OK;
+}
+
+tg_status tg_serve_stream_arena(tg_server* s, int32_t stream_id, int64_t max_n, tg_gaussians* out) {
+  if (!s || !out || max_n < 1) return TG_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->arenas.find(stream_id);
+  if (it == s->arenas.end()) {
+    const int64_t bytes = max_n * (44 + 4 * (int64_t)s->opts.c);
+    if (s->budget_used + bytes > s->opts.budget_bytes) return TG_ERR_BUDGET;
+    if (hipSetDevice(s->device) != hipSuccess) return TG_ERR_HIP;
+    Arena a;
+    a.max_n = max_n;
+    a.bytes = bytes;
+    if (!dalloc(&a.mean, 3 * max_n) || !dalloc(&a.scale, 3 * max_n) || !dalloc(&a.quat, 4 * max_n) ||
+        !dalloc(&a.opacity, max_n) || !dalloc(&a.feat, max_n * s->opts.c)) {
+      float* p[] = {a.mean, a.scale, a.quat, a.opacity, a.feat};
+      for (float* x : p)
+        if (x) (void)hipFree(x);
+      return TG_ERR_OOM;
+    }
+    s->budget_used += bytes;
+    it = s->arenas.emplace(stream_id, a).first;
+  } else if (max_n > it->second.max_n) {
+    return TG_ERR_INVALID;
+  }
+  const Arena& a = it->second;
+  out->mean = a.mean; out->scale = a.scale; out->quat = a.quat; out->opacity = a.opacity; out->feat = a.feat;
+  out->n = a.max_n;
+  out->c = s->opts.c;
+  return TG_OK;
+}
+
+tg_status tg_serve_submit(tg_server* s, const tg_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket) return TG_ERR_INVALID;
+  const tg_gaussians& g = req->g;
+  if (g.c != s->opts.c || g.n < 0 || (g.n > 0 && (!g.mean || !g.scale || !g.quat || !g.opacity || !g.feat)) ||
+      !req->out_feat || req->cam.width <= 0 || req->cam.height <= 0 || req->cam.width > s->opts.max_side ||
+      req->cam.height > s->opts.max_side)
+    return TG_ERR_INVALID;
+  Ticket t;
+  t.req = *req;
+  t.footprint = footprint_of(s, *req);
+  t.t_submit = now_ns();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop || s->failed) return TG_ERR_INVALID;
+  if (tg::padded(g.n) > s->cap_gauss || (int64_t)req->cam.width * req->cam.height > s->cap_pixels ||
+      tiles_of(req->cam) > s->cap_tiles || t.footprint > s->opts.budget_bytes)
+    return TG_ERR_BUDGET;
+  const uint64_t id = s->next_ticket++;
+  s->tickets.emplace(id, t);
+  s->queue.push_back(id);
+  *ticket = id;
+  s->cv.notify_one();
+  return TG_OK;
+}
+
+static void fill_result(const Ticket& t, tg_result* out) {
+  if (!out) return;
+  out->status = t.status;
+  out->batch_size = t.batch_size;
+  out->slot = t.slot;
+  out->retries = t.retries;
+  out->t_submit_ns = t.t_submit;
+  out->t_launch_ns = t.t_launch;
+  out->t_done_ns = t.t_done;
+}
+
+tg_status tg_serve_poll(tg_server* s, uint64_t ticket, tg_result* out) {
+  if (!s) return TG_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return TG_ERR_NOT_FOUND;
+  fill_result(it->second, out);
+  return (tg_status)it->second.status;
+}
+
+tg_status tg_serve_wait(tg_server* s, uint64_t ticket, tg_result* out) {
+  if (!s) return TG_ERR_INVALID;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return TG_ERR_NOT_FOUND;
+  s->done_cv.wait(lk, [&] { return s->tickets[ticket].status != TG_PENDING; });
+  const Ticket& t = s->tickets[ticket];
+  fill_result(t, out);
+  return (tg_status)t.status;
+}
+
+tg_status tg_serve_release(tg_server* s, uint64_t ticket) {
+  if (!s) return TG_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return TG_ERR_NOT_FOUND;
+  if (it->second.status == TG_PENDING) return TG_PENDING;
+  s->tickets.erase(it);
+  return TG_OK;
+}
+
+void tg_serve_destroy(tg_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->sched.joinable()) s->sched.join();
+  (void)hipSetDevice(s->device);
+  (void)hipDeviceSynchronize();
+  for (Slot& sl : s->slots) free_slot(sl);
+  for (auto& kv : s->arenas) {
+    float* p[] = {kv.second.mean, kv.second.scale, kv.second.quat, kv.second.opacity, kv.second.feat};
+    for (float* x : p)
+      if (x) (void)hipFree(x);
+  }
+  delete s;
+}
+
+}  // extern "C"

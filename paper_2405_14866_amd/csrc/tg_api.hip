@@ -32,9 +32,11 @@ struct tg_frame {
   int32_t* sorted = nullptr;
   float* T_final = nullptr;
   int32_t* last = nullptr;
-  float* g2d = nullptr;          // [6][max_n] backward accumulators
+  float* g2d = nullptr;          // [6][g_cap] backward accumulators
   tg::FrameDev* dev = nullptr;
+  int64_t g_cap = 0;             // padded Gaussian capacity
   // state of the last projection / render
+  tg::ReqDev req{};
   int64_t n = -1;
   int32_t c = 0;
   tg::CamArgs cam{};
@@ -44,8 +46,8 @@ struct tg_frame {
 };
 
 namespace tg {
-hipError_t bin_set_attributes();
-}
+int ctx_device(const tg_ctx* c) { return c->device; }
+}  // namespace tg
 
 namespace {
 
@@ -90,19 +92,27 @@ tg_status check_gaussians(const tg_frame* f, const tg_gaussians* g, bool need_c)
   return TG_OK;
 }
 
-tg::BinArgs bin_args(tg_frame* f) {
-  tg::BinArgs b;
+// Kernel arguments of a frame: a batch of one request passed inline.
+tg::BatchArgs frame_args(tg_frame* f) {
+  tg::BatchArgs b{};
+  b.table = nullptr;
+  b.hdr_dev = nullptr;
+  b.one = f->req;
+  b.hdr.n_req = 1;
+  b.hdr.n_tiles = f->n_tiles;
+  b.hdr.g_end = tg::padded(f->n);
+  b.xy = f->xy;
+  b.conic_o = f->conic_o;
   b.rect = f->rect;
   b.depth = f->depth;
-  b.n = f->n;
-  b.tiles_x = f->cam.tiles_x;
-  b.n_tiles = f->n_tiles;
   b.tile_count = f->tile_count;
   b.tile_start = f->tile_start;
   b.tile_cursor = f->tile_cursor;
   b.keys = f->keys;
   b.keys_tmp = f->keys_tmp;
   b.sorted = f->sorted;
+  b.g2d = f->g2d;
+  b.g_cap = f->g_cap;
   b.key_cap = f->max_keys;
   b.dev = f->dev;
   return b;
@@ -162,11 +172,12 @@ tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max
   const int64_t tx = (max_w + tg::TILE - 1) / tg::TILE, ty = (max_h + tg::TILE - 1) / tg::TILE;
   f->max_tiles = (int32_t)(tx * ty);
   const size_t npix = (size_t)max_w * max_h;
+  f->g_cap = tg::padded(max_n > 0 ? max_n : 1);
   tg_status st = TG_OK;
-  if (st == TG_OK) st = dalloc(&f->xy, max_n);
-  if (st == TG_OK) st = dalloc(&f->conic_o, max_n);
-  if (st == TG_OK) st = dalloc(&f->rect, max_n);
-  if (st == TG_OK) st = dalloc(&f->depth, max_n);
+  if (st == TG_OK) st = dalloc(&f->xy, f->g_cap);
+  if (st == TG_OK) st = dalloc(&f->conic_o, f->g_cap);
+  if (st == TG_OK) st = dalloc(&f->rect, f->g_cap);
+  if (st == TG_OK) st = dalloc(&f->depth, f->g_cap);
   if (st == TG_OK) st = dalloc(&f->tile_count, f->max_tiles);
   if (st == TG_OK) st = dalloc(&f->tile_start, (size_t)f->max_tiles + 1);
   if (st == TG_OK) st = dalloc(&f->tile_cursor, f->max_tiles);
@@ -175,7 +186,7 @@ tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max
   if (st == TG_OK) st = dalloc(&f->sorted, max_keys);
   if (st == TG_OK) st = dalloc(&f->T_final, npix);
   if (st == TG_OK) st = dalloc(&f->last, npix);
-  if (st == TG_OK) st = dalloc(&f->g2d, (size_t)6 * max_n);
+  if (st == TG_OK) st = dalloc(&f->g2d, (size_t)6 * f->g_cap);
   if (st == TG_OK) st = dalloc(&f->dev, 1);
   if (st == TG_OK && hipMemset(f->dev, 0, sizeof(tg::FrameDev)) != hipSuccess) st = TG_ERR_HIP;
   if (st == TG_OK && hipMemset(f->tile_start, 0, ((size_t)f->max_tiles + 1) * sizeof(int32_t)) != hipSuccess)
@@ -216,16 +227,15 @@ tg_status tg_project(tg_frame* f, const tg_gaussians* g, const tg_camera* cam, v
   f->n = g->n;
   f->n_tiles = c.tiles_x * c.tiles_y;
   f->binned = f->rendered = false;
-  tg::ProjectArgs a;
-  a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.opacity = g->opacity;
-  a.n = g->n;
-  a.cam = c;
-  a.xy = f->xy; a.conic_o = f->conic_o; a.rect = f->rect; a.depth = f->depth;
-  a.tile_count = f->tile_count;
-  a.n_tiles = f->n_tiles;
+  tg::ReqDev& q = f->req;
+  q = tg::ReqDev{};
+  q.mean = g->mean; q.scale = g->scale; q.quat = g->quat; q.opacity = g->opacity; q.feat = g->feat;
+  q.T_final = f->T_final; q.last = f->last;
+  q.n = g->n; q.g_off = 0; q.tile_off = 0;
+  q.cam = c;
   hipStream_t s = static_cast<hipStream_t>(stream);
   f->last_stream = s;
-  return tg::launch_project(a, s) == hipSuccess ? TG_OK : TG_ERR_HIP;
+  return tg::launch_project(frame_args(f), tg::padded(g->n), s) == hipSuccess ? TG_OK : TG_ERR_HIP;
 }
 
 tg_status tg_bin_sort(tg_frame* f, void* stream) {
@@ -233,7 +243,8 @@ tg_status tg_bin_sort(tg_frame* f, void* stream) {
   DeviceGuard guard(f->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   f->last_stream = s;
-  if (tg::launch_bin_sort(bin_args(f), s) != hipSuccess) return TG_ERR_HIP;
+  if (tg::launch_bin_sort(frame_args(f), tg::padded(f->n), f->n_tiles, f->n_tiles, s) != hipSuccess)
+    return TG_ERR_HIP;
   f->binned = true;
   return TG_OK;
 }
@@ -245,18 +256,15 @@ static tg_status render_fwd_impl(tg_frame* f, const tg_gaussians* g, const float
   if (st != TG_OK) return st;
   if (g->n != f->n) return TG_ERR_INVALID;
   DeviceGuard guard(f->device);
-  tg::RenderArgs a;
-  a.xy = f->xy; a.conic_o = f->conic_o; a.feat = g->feat;
-  a.tile_start = f->tile_start; a.sorted = f->sorted;
-  a.bg = bg;
-  a.out_feat = out_feat; a.out_alpha = out_alpha;
-  a.T_final = f->T_final; a.last = f->last;
-  a.W = f->cam.W; a.H = f->cam.H; a.tiles_x = f->cam.tiles_x; a.n_tiles = f->n_tiles;
-  a.dev = f->dev;
+  tg::ReqDev& q = f->req;
+  q.feat = g->feat;
+  q.bg = bg;
+  q.out_feat = out_feat;
+  q.out_alpha = out_alpha;
   hipStream_t s = static_cast<hipStream_t>(stream);
   f->last_stream = s;
   f->c = g->c;
-  if (tg::launch_render_fwd(a, g->c, s, count) != hipSuccess) return TG_ERR_HIP;
+  if (tg::launch_render_fwd(frame_args(f), g->c, f->n_tiles, s, count) != hipSuccess) return TG_ERR_HIP;
   f->rendered = true;
   return TG_OK;
 }
@@ -291,24 +299,18 @@ tg_status tg_render_bwd(tg_frame* f, const tg_gaussians* g, const float* bg, con
   DeviceGuard guard(f->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   f->last_stream = s;
-  if (tg::launch_fill_zero(f->g2d, 6 * g->n, s) != hipSuccess) return TG_ERR_HIP;
-  if (tg::launch_fill_zero(out->d_feat, g->n * (int64_t)g->c, s) != hipSuccess) return TG_ERR_HIP;
-  tg::BackwardArgs b;
-  b.xy = f->xy; b.conic_o = f->conic_o; b.feat = g->feat;
-  b.tile_start = f->tile_start; b.sorted = f->sorted; b.bg = bg;
-  b.T_final = f->T_final; b.last = f->last;
-  b.d_img = d_feat; b.d_alpha = d_alpha;
-  b.g2d = f->g2d; b.g_feat = out->d_feat;
-  b.n = g->n;
-  b.W = f->cam.W; b.H = f->cam.H; b.tiles_x = f->cam.tiles_x; b.n_tiles = f->n_tiles;
-  b.dev = f->dev;
-  if (tg::launch_render_bwd(b, g->c, s) != hipSuccess) return TG_ERR_HIP;
-  tg::ProjectBwdArgs p;
-  p.mean = g->mean; p.scale = g->scale; p.quat = g->quat; p.opacity = g->opacity;
-  p.n = g->n; p.cam = f->cam; p.rect = f->rect; p.g2d = f->g2d;
-  p.d_mean = out->d_mean; p.d_log_scale = out->d_log_scale; p.d_quat = out->d_quat;
-  p.d_logit = out->d_opacity_logit;
-  if (tg::launch_project_bwd(p, s) != hipSuccess) return TG_ERR_HIP;
+  tg::ReqDev& q = f->req;
+  q.feat = g->feat;
+  q.bg = bg;
+  q.d_img = d_feat;
+  q.d_alpha = d_alpha;
+  q.d_mean = out->d_mean;
+  q.d_log_scale = out->d_log_scale;
+  q.d_quat = out->d_quat;
+  q.d_logit = out->d_opacity_logit;
+  q.d_feat = out->d_feat;
+  if (tg::launch_render_bwd(frame_args(f), g->c, tg::padded(f->n), f->n_tiles, s) != hipSuccess)
+    return TG_ERR_HIP;
   return TG_OK;
 }
 

@@ -1,19 +1,28 @@
 // tg_internal.h -- device data layout and kernel launchers of libtg (gfx950).
 //
-// Frame workspace in HBM (all structure-of-arrays, allocated once per frame):
+// Every kernel works on a *batch* of render requests (a single render is a
+// batch of one).  A batch is one virtual frame:
+//   * a global Gaussian index space: request r owns indices
+//     [g_off, g_off + n) with g_off a multiple of BIN_CHUNK, so a
+//     workgroup that covers an aligned chunk of indices never straddles
+//     two requests;
+//   * a global tile space: request r owns tiles [tile_off, tile_off +
+//     tiles_x * tiles_y) in row-major order of its own image.
+// Workspace in HBM (structure of arrays, allocated once per frame / slot):
 //   per Gaussian  xy      double2  projected mean (u, v) in pixels, FP64 so
 //                                  that the render's pixel offsets are exact
 //                 conic_o float4   (A, B, C, opacity); conic = Sigma'^-1
 //                 rect    uint2    tile rectangle, x0 | x1 << 16, y0 | y1 << 16
 //                                  (empty: x0 > x1)
 //                 depth   uint32   IEEE bits of the float32 view depth
+//                 g2d     float    [6][cap] backward accumulators
 //   per tile      count, start[n_tiles + 1], cursor       int32
-//   per key       keys    uint64   (depth << 32) | index, grouped by tile
+//   per key       keys    uint64   (depth << 32) | global index, grouped by tile
 //                 keys_tmp uint64  scratch for segments too long for LDS
-//                 sorted  int32    Gaussian index, per tile in (depth, index) order
-//   per pixel     T_final float32, last int32 (read by the backward pass)
-//   per Gaussian  grad2d  float    [8][n] accumulators of the backward pass
-//   device state  FrameDev (overflow flag, key count)
+//                 sorted  int32    global index, per tile in (depth, index) order
+//   per pixel     T_final float32, last int32 (read by the backward pass),
+//                 one slice per request
+//   device state  FrameDev (overflow flag, key count, work queue, counters)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,12 +31,16 @@
 namespace tg {
 
 constexpr int TILE = 16;
-constexpr int SORT_LDS_CAP = 4096;     // keys sorted entirely in LDS per tile
 constexpr int BIN_LDS_MAX_TILES = 32768;  // per-tile counters kept in LDS (128 KB)
-constexpr int BIN_CHUNK = 1024;        // Gaussians per binning workgroup
+constexpr int BIN_CHUNK = 1024;           // Gaussians per binning workgroup (and index alignment)
+constexpr int MAX_BATCH = 64;             // requests per batch
 
 struct FrameDev {
   int32_t overflow;             // set when the binning needs more keys than the frame holds
+  int32_t tile_queue;           // next tile of the persistent forward loop
+  int32_t tile_done;            // forward workgroups finished (the last one resets both)
+  int32_t bwd_queue;            // next tile of the persistent backward loop
+  int32_t bwd_done;             // backward workgroups finished (the last one resets both)
   int32_t pad;
   int64_t n_keys;               // keys needed by the last binning
   // work of the last counted render
@@ -44,93 +57,107 @@ struct CamArgs {
   int32_t W, H, tiles_x, tiles_y;
 };
 
-struct ProjectArgs {
-  const float* mean;
-  const float* scale;
-  const float* quat;
-  const float* opacity;
+// One render request of a batch.
+struct ReqDev {
+  const float* mean;     // [3][n]
+  const float* scale;    // [3][n]
+  const float* quat;     // [4][n]
+  const float* opacity;  // [n]
+  const float* feat;     // [n][c]
+  const float* bg;       // [c] or null
+  float* out_feat;       // [c][H][W]
+  float* out_alpha;      // [H][W] or null
+  float* T_final;        // [H][W] (workspace slice)
+  int32_t* last;         // [H][W] (workspace slice)
+  // backward
+  const float* d_img;    // [c][H][W]
+  const float* d_alpha;  // [H][W] or null
+  float* d_mean;         // [3][n] or null
+  float* d_log_scale;    // [3][n] or null
+  float* d_quat;         // [4][n] or null
+  float* d_logit;        // [n] or null
+  float* d_feat;         // [n][c]
   int64_t n;
+  int64_t g_off;         // first global Gaussian index (multiple of BIN_CHUNK)
+  int32_t tile_off;      // first global tile
+  int32_t pad;
   CamArgs cam;
+};
+
+// Totals of a batch (device copy for replayed launches, inline otherwise).
+struct BatchHdr {
+  int32_t n_req;
+  int32_t n_tiles;       // sum of the requests' tiles
+  int64_t g_end;         // end of the padded global Gaussian index space
+};
+
+// Kernel arguments shared by every step.  A single render passes its
+// request inline (table == nullptr); a replayed batch reads the request
+// table and the header from device memory.
+struct BatchArgs {
+  const ReqDev* table;
+  const BatchHdr* hdr_dev;
+  ReqDev one;
+  BatchHdr hdr;
+  // workspace
   double2* xy;
   float4* conic_o;
   uint2* rect;
   uint32_t* depth;
-  int32_t* tile_count;
-  int32_t n_tiles;
-};
-
-struct BinArgs {
-  const uint2* rect;
-  const uint32_t* depth;
-  int64_t n;
-  int32_t tiles_x, n_tiles;
   int32_t* tile_count;
   int32_t* tile_start;
   int32_t* tile_cursor;
   uint64_t* keys;
   uint64_t* keys_tmp;
   int32_t* sorted;
+  float* g2d;            // [6][g_cap]
+  int64_t g_cap;         // capacity of the global Gaussian index space
   int64_t key_cap;
   FrameDev* dev;
 };
 
-struct RenderArgs {
-  const double2* xy;
-  const float4* conic_o;
-  const float* feat;     // [n][c]
-  const int32_t* tile_start;
-  const int32_t* sorted;
-  const float* bg;       // [c] or null
-  float* out_feat;       // [c][H][W]
-  float* out_alpha;      // [H][W]
-  float* T_final;        // [H][W]
-  int32_t* last;         // [H][W]
-  int32_t W, H, tiles_x, n_tiles;
-  FrameDev* dev;
-};
+__device__ __forceinline__ BatchHdr batch_hdr(const BatchArgs& a) {
+  return a.table ? *a.hdr_dev : a.hdr;
+}
 
-struct BackwardArgs {
-  // forward state
-  const double2* xy;
-  const float4* conic_o;
-  const float* feat;
-  const int32_t* tile_start;
-  const int32_t* sorted;
-  const float* bg;
-  const float* T_final;
-  const int32_t* last;
-  // upstream
-  const float* d_img;    // [c][H][W]
-  const float* d_alpha;  // [H][W] or null
-  // outputs: 2D-state gradients [6][n] (du, dv, dA, dB, dC, dopacity) and features [n][c]
-  float* g2d;
-  float* g_feat;
-  int64_t n;
-  int32_t W, H, tiles_x, n_tiles;
-  const FrameDev* dev;
-};
+__device__ __forceinline__ const ReqDev& batch_req(const BatchArgs& a, int r) {
+  return a.table ? a.table[r] : a.one;
+}
 
-struct ProjectBwdArgs {
-  const float* mean;
-  const float* scale;
-  const float* quat;
-  const float* opacity;
-  int64_t n;
-  CamArgs cam;
-  const uint2* rect;
-  const float* g2d;      // [6][n]
-  float* d_mean;         // [3][n]
-  float* d_log_scale;    // [3][n]
-  float* d_quat;         // [4][n]
-  float* d_logit;        // [n]
-};
+// request that owns global Gaussian index g of the padded space, or -1
+__device__ __forceinline__ int req_of_gauss(const BatchArgs& a, const BatchHdr& h, int64_t g) {
+  if (g >= h.g_end) return -1;
+  if (!a.table) return 0;
+  for (int r = h.n_req - 1; r >= 0; --r)
+    if (g >= a.table[r].g_off) return r;
+  return -1;
+}
 
-// launchers (return hipSuccess or the launch error)
-hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
-hipError_t launch_bin_sort(const BinArgs& a, hipStream_t s);
-hipError_t launch_render_fwd(const RenderArgs& a, int c, hipStream_t s, bool count_work = false);
-hipError_t launch_render_bwd(const BackwardArgs& a, int c, hipStream_t s);
-hipError_t launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
+// request that owns global tile t, or -1
+__device__ __forceinline__ int req_of_tile(const BatchArgs& a, const BatchHdr& h, int t) {
+  if (t >= h.n_tiles) return -1;
+  if (!a.table) return 0;
+  for (int r = h.n_req - 1; r >= 0; --r)
+    if (t >= a.table[r].tile_off) return r;
+  return -1;
+}
+
+__host__ __device__ inline int64_t padded(int64_t n) {
+  return (n + BIN_CHUNK - 1) / BIN_CHUNK * BIN_CHUNK;
+}
+
+// Launchers; they return hipSuccess or the launch error.  Grids are sized
+// from grid_gauss (padded Gaussian capacity) and grid_tiles (tile
+// capacity): exact for a single render, the slot capacity for a replayed
+// batch (workgroups beyond the batch's totals return at once).
+hipError_t launch_project(const BatchArgs& a, int64_t grid_gauss, hipStream_t s);
+hipError_t launch_bin_sort(const BatchArgs& a, int64_t grid_gauss, int32_t grid_tiles,
+                           int32_t max_tiles_per_req, hipStream_t s);
+hipError_t launch_render_fwd(const BatchArgs& a, int c, int32_t grid_tiles, hipStream_t s,
+                             bool count_work = false);
+hipError_t launch_render_bwd(const BatchArgs& a, int c, int64_t grid_gauss, int32_t grid_tiles,
+                             hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+hipError_t bin_set_attributes();
 
 }  // namespace tg

@@ -43,7 +43,8 @@ def compare_lists(gpu, ora):
     np.testing.assert_array_equal(gpu["sorted"], lst)
 
 
-def compare_forward(gpu, ora, ref=None, bg=None, tol_feat=TOL_FEAT, tol_alpha=TOL_ALPHA):
+def compare_forward(gpu, ora, ref=None, bg=None, tol_feat=TOL_FEAT, tol_alpha=TOL_ALPHA,
+                    check_last=True):
     """Element-wise forward parity.  Pixels with a near-threshold decision
     (flagged by the oracle) must match one of the oracle's branch variants.
     Returns a small report dict."""
@@ -58,7 +59,8 @@ def compare_forward(gpu, ora, ref=None, bg=None, tol_feat=TOL_FEAT, tol_alpha=TO
         f"{bad.sum()} unflagged pixels off: max dF {dF[~flagged].max():.3g} "
         f"max dA {dA[~flagged].max():.3g} at {np.argwhere(bad)[:5].tolist()}")
     # last contributor is an index: exact where no decision was near a threshold
-    np.testing.assert_array_equal(gpu["last"][~flagged], ref["last"][~flagged])
+    if check_last:
+        np.testing.assert_array_equal(gpu["last"][~flagged], ref["last"][~flagged])
     excluded = 0
     for (y, x) in np.argwhere(flagged & ~ok):
         var = ora.pixel_variants(int(x), int(y), bg=bg)

@@ -1,0 +1,197 @@
+"""GPU tests of the serving loop (tg_serve_*): every request's result is the
+same alone (plain path) and in the mix of a batch, the budget and the key
+capacity are enforced, graph replay equals direct launches, and requests
+submitted from several threads all complete."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from gpu_common import compare_forward, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(k=6, c=32, seed=100):
+    """Uneven Gaussian counts, resolutions and poses (the serving generator,
+    scaled down)."""
+    out = []
+    rng = np.random.default_rng(seed)
+    for i in range(k):
+        n = int(rng.integers(2000, 20000))
+        res = int(rng.choice([64, 96, 128]))
+        g = int(np.ceil(np.sqrt(n)))
+        sc = scenes.make_grid_scene(seed + i, g, float(g), c, res, float(res),
+                                    yaw=float(rng.uniform(-10, 10)), pitch=float(rng.uniform(-5, 5)), n=n)
+        out.append(sc)
+    return out
+
+
+def _alone(scenes_, torch):
+    from paper_2405_14866_amd.rasterize import GaussianSoA, Rasterizer
+    res = []
+    for sc in scenes_:
+        g = GaussianSoA.from_scene(sc)
+        r = Rasterizer(0, max_n=sc.n, max_w=sc.cam.width, max_h=sc.cam.height)
+        f, a = r.forward(g, sc.cam)
+        res.append((f.cpu().numpy(), a.cpu().numpy()))
+    return res
+
+
+def _served(server, scenes_, torch, bg=None):
+    from paper_2405_14866_amd.rasterize import GaussianSoA
+    outs, tickets = [], []
+    for i, sc in enumerate(scenes_):
+        g = GaussianSoA.from_scene(sc)
+        f = torch.empty((sc.c, sc.cam.height, sc.cam.width), device="cuda")
+        a = torch.empty((sc.cam.height, sc.cam.width), device="cuda")
+        tickets.append(server.submit(g, sc.cam, f, a, bg=bg, stream_id=i % 3))
+        outs.append((f, a))
+    results = [server.wait(t) for t in tickets]
+    return [(f.cpu().numpy(), a.cpu().numpy()) for f, a in outs], results
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_alone_equals_in_the_mix(use_graph):
+    torch = torch_cuda()
+    from paper_2405_14866_amd.serve import Server
+    reqs = _requests()
+    alone = _alone(reqs, torch)
+    srv = Server(0, c=32, slots=2, max_batch=4, max_gauss_per_batch=60000, max_keys_per_batch=600000,
+                 max_pixels_per_batch=4 * 128 * 128, max_side=128, use_graph=use_graph)
+    served, results = _served(srv, reqs, torch)
+    srv.close()
+    assert all(r.status == 0 for r in results), [r.status for r in results]
+    assert max(r.batch_size for r in results) > 1          # requests were really batched
+    for (fa, aa), (fs, as_) in zip(alone, served):
+        # same kernels, same per-request lists: expected bitwise; the bar is the tolerance
+        assert np.abs(fa - fs).max() <= 2e-4 and np.abs(aa - as_).max() <= 1e-5
+    bitwise = all(np.array_equal(fa, fs) and np.array_equal(aa, as_) for (fa, aa), (fs, as_) in zip(alone, served))
+    print("bitwise identical alone vs in the mix:", bitwise)
+    assert bitwise
+
+
+def test_served_request_matches_oracle():
+    torch = torch_cuda()
+    from paper_2405_14866_amd.serve import Server
+    reqs = _requests(3, c=8, seed=300)
+    bg = np.linspace(-1, 1, 8).astype(np.float32)
+    srv = Server(0, c=8, slots=1, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=600000,
+                 max_pixels_per_batch=3 * 128 * 128, max_side=128)
+    served, results = _served(srv, reqs, torch, bg=torch.as_tensor(bg, device="cuda"))
+    srv.close()
+    assert results[0].batch_size == 3
+    for sc, (f, a) in zip(reqs, served):
+        ora = oracle.Oracle(sc)
+        compare_forward(dict(feat=f, alpha=a, last=_last_placeholder(ora, sc, bg)), ora,
+                        bg=bg.astype(np.float64), check_last=False)
+
+
+def _last_placeholder(ora, sc, bg):
+    return np.zeros((sc.cam.height, sc.cam.width), np.int32)
+
+
+def test_budget_and_capacity():
+    torch = torch_cuda()
+    from paper_2405_14866_amd import _native as N
+    from paper_2405_14866_amd.rasterize import GaussianSoA
+    from paper_2405_14866_amd.serve import Server
+    reqs = _requests(4, seed=500)
+    alone = _alone(reqs, torch)
+    # a budget that holds one request at a time: everything still completes, one per batch
+    # (bytes a request occupies in flight: padded state, estimated keys, pixel state and outputs)
+    fp = lambda sc: (-(-sc.n // 1024) * 1024) * 44 + (int(sc.n * 5.0) + 1024) * 20 + \
+        sc.cam.width * sc.cam.height * (8 + 4 * 33)
+    budget = max(fp(sc) for sc in reqs)
+    srv = Server(0, c=32, slots=2, max_batch=4, max_gauss_per_batch=60000, max_keys_per_batch=600000,
+                 max_pixels_per_batch=4 * 128 * 128, max_side=128, budget_bytes=budget)
+    served, results = _served(srv, reqs, torch)
+    assert all(r.status == 0 and r.batch_size == 1 for r in results)
+    for (fa, aa), (fs, as_) in zip(alone, served):
+        assert np.array_equal(fa, fs)
+    # a request larger than the budget is refused at submit
+    big = scenes.make_grid_scene(7, 200, 200.0, 32, 128, 128.0)
+    g = GaussianSoA.from_scene(big)
+    f = torch.empty((32, 128, 128), device="cuda")
+    with pytest.raises(N.TgError) as ei:
+        srv.submit(g, big.cam, f)
+    assert ei.value.status == N.TG_ERR_BUDGET
+    # a target larger than max_side is invalid
+    cam = scenes.Camera(big.cam.R, big.cam.t, 64, 64, 64, 64, 256, 256)
+    with pytest.raises(N.TgError):
+        srv.submit(g, cam, torch.empty((32, 256, 256), device="cuda"))
+    srv.close()
+
+
+def test_key_overflow_is_readmitted_alone():
+    """A batch that overflows the slot's key capacity is re-admitted one
+    request at a time; a request that overflows alone fails."""
+    torch = torch_cuda()
+    from paper_2405_14866_amd.serve import Server
+    reqs = _requests(3, seed=700)
+    alone = _alone(reqs, torch)
+    from paper_2405_14866_amd.rasterize import GaussianSoA, Rasterizer
+    nk = []
+    for sc in reqs:
+        r = Rasterizer(0, max_n=sc.n, max_w=sc.cam.width, max_h=sc.cam.height)
+        r.forward(GaussianSoA.from_scene(sc), sc.cam)
+        nk.append(r.n_keys)
+    cap = max(nk) + 16                       # every request fits alone, the batch does not
+    assert sum(nk) > cap
+    srv = Server(0, c=32, slots=1, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=cap,
+                 max_pixels_per_batch=3 * 128 * 128, max_side=128, keys_per_gaussian=1e-3)
+    served, results = _served(srv, reqs, torch)
+    assert all(r.status == 0 for r in results)
+    assert any(r.retries > 0 for r in results)
+    for (fa, aa), (fs, as_) in zip(alone, served):
+        assert np.array_equal(fa, fs)
+    srv.close()
+    srv = Server(0, c=32, slots=1, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=min(nk) // 2,
+                 max_pixels_per_batch=3 * 128 * 128, max_side=128, keys_per_gaussian=1e-3)
+    _, results = _served(srv, reqs[:1], torch)
+    from paper_2405_14866_amd import _native as N
+    assert results[0].status == N.TG_ERR_CAPACITY
+    srv.close()
+
+
+def test_threads_submit_concurrently():
+    torch = torch_cuda()
+    from paper_2405_14866_amd.rasterize import GaussianSoA
+    from paper_2405_14866_amd.serve import Server
+    reqs = _requests(8, c=16, seed=900)
+    gs = [GaussianSoA.from_scene(sc) for sc in reqs]
+    outs = [torch.empty((16, sc.cam.height, sc.cam.width), device="cuda") for sc in reqs]
+    torch.cuda.synchronize()
+    srv = Server(0, c=16, slots=3, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=600000,
+                 max_pixels_per_batch=3 * 128 * 128, max_side=128)
+    tickets = [None] * len(reqs)
+
+    def client(k):
+        for i in range(k, len(reqs), 4):
+            tickets[i] = srv.submit(gs[i], reqs[i].cam, outs[i], stream_id=k)
+
+    th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    results = [srv.wait(t) for t in tickets]
+    assert all(r.status == 0 for r in results)
+    assert all(r.t_submit_ns <= r.t_launch_ns <= r.t_done_ns for r in results)
+    srv.close()
+
+
+def test_stream_arena_is_resident_and_budgeted():
+    torch = torch_cuda()
+    from paper_2405_14866_amd import _native as N
+    from paper_2405_14866_amd.serve import Server
+    srv = Server(0, c=8, slots=1, max_batch=2, max_gauss_per_batch=10000, max_keys_per_batch=100000,
+                 max_pixels_per_batch=2 * 64 * 64, max_side=64, budget_bytes=4 << 20)
+    a = srv.stream_arena(3, 5000)
+    b = srv.stream_arena(3, 4000)
+    assert a.mean and a.mean == b.mean and a.n == 5000 and a.c == 8
+    with pytest.raises(N.TgError):
+        srv.stream_arena(4, 1 << 20)         # would exceed the 4 MiB budget
+    srv.close()
