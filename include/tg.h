@@ -208,6 +208,9 @@ typedef struct tg_serve_opts {
   int32_t c;                    /* channel count of every request: 8, 16, 32 or 64 */
   int32_t use_graph;            /* 1: replay a captured HIP graph per slot; 0: launch directly */
   float keys_per_gaussian;      /* key estimate per Gaussian used for admission */
+  int32_t batch_window_us;      /* a free slot waits up to this long after the oldest queued
+                                   request arrived for more requests before it launches a
+                                   batch of fewer than max_batch (0: launch at once), 0..1e6 */
 } tg_serve_opts;
 
 /* One render request.  g points at device buffers that the caller keeps

@@ -55,7 +55,8 @@ class tg_serve_opts(ct.Structure):
     _fields_ = [("budget_bytes", ct.c_int64), ("slots", ct.c_int32), ("max_batch", ct.c_int32),
                 ("max_gauss_per_batch", ct.c_int64), ("max_keys_per_batch", ct.c_int64),
                 ("max_pixels_per_batch", ct.c_int64), ("max_side", ct.c_int32), ("c", ct.c_int32),
-                ("use_graph", ct.c_int32), ("keys_per_gaussian", ct.c_float)]
+                ("use_graph", ct.c_int32), ("keys_per_gaussian", ct.c_float),
+                ("batch_window_us", ct.c_int32)]
 
 
 class tg_request(ct.Structure):

@@ -8,7 +8,8 @@
 //     the streams' resident arenas stay within the budget, and while the
 //     slot's capacities (Gaussians, keys, tiles, pixels) hold;
 //   * whenever a slot is free it forms a batch of everything admissible (up
-//     to max_batch requests) and launches it: the request table goes to
+//     to max_batch requests; with a batching window, a batch of fewer
+//     waits until the oldest queued request is that old) and launches it: the request table goes to
 //     the device by one pinned copy, then one launch per step (projection,
 //     binning, sort, blend) covers every request of the batch - the kernels
 //     read the table, their grids are the slot's capacity and the blend is a
@@ -122,7 +123,8 @@ struct tg_server {
   std::unordered_map<uint64_t, Ticket> tickets;
   std::unordered_map<int32_t, Arena> arenas;
   uint64_t next_ticket = 1;
-  int64_t budget_used = 0;
+  int64_t budget_used = 0;            // arenas + requests in flight
+  int64_t arena_bytes = 0;            // arenas alone (held for the server's lifetime)
   bool stop = false;
   std::thread sched;
   bool failed = false;               // a HIP error stopped the scheduler
@@ -348,7 +350,16 @@ void scheduler(tg_server* s) {
         s->done_cv.notify_all();
       }
     }
-    if (!s->stop && !s->failed) {
+    // batching window: while fewer than max_batch requests are queued, hold
+    // them until the oldest has waited batch_window_us
+    bool hold = false;
+    int64_t deadline = 0;
+    if (!s->queue.empty() && s->opts.batch_window_us > 0 && (int)s->queue.size() < s->opts.max_batch) {
+      const Ticket& front = s->tickets[s->queue.front()];
+      deadline = front.t_submit + (int64_t)s->opts.batch_window_us * 1000;
+      hold = !front.solo && now_ns() < deadline;
+    }
+    if (!s->stop && !s->failed && !hold) {
       for (size_t i = 0; i < s->slots.size() && !s->queue.empty(); ++i)
         if (!s->slots[i].busy && launch_batch(s, (int)i)) any_busy = true;
     }
@@ -359,6 +370,9 @@ void scheduler(tg_server* s) {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
       lk.lock();
+    } else if (hold && !s->stop && !s->failed) {
+      // woken early by a submit; the loop re-evaluates the window
+      s->cv.wait_until(lk, std::chrono::steady_clock::time_point(std::chrono::nanoseconds(deadline)));
     } else {
       s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
     }
@@ -385,6 +399,7 @@ tg_status tg_serve_create(tg_ctx* ctx, const tg_serve_opts* opts, tg_server** ou
       o.max_gauss_per_batch < 1 || o.max_keys_per_batch < 1 || o.max_keys_per_batch >= ((int64_t)1 << 31) ||
       o.max_pixels_per_batch < 1 || o.max_side < 1 || o.max_side > 65535 * tg::TILE || o.budget_bytes <= 0 ||
       !(o.c == 8 || o.c == 16 || o.c == 32 || o.c == 64) || !(o.keys_per_gaussian > 0.f) ||
+      o.batch_window_us < 0 || o.batch_window_us > 1000000 ||
       o.max_gauss_per_batch >= ((int64_t)1 << 31))
     return TG_ERR_INVALID;
   const int device = tg::ctx_device(ctx);
@@ -432,6 +447,7 @@ tg_status tg_serve_stream_arena(tg_server* s, int32_t stream_id, int64_t max_n, 
       return TG_ERR_OOM;
     }
     s->budget_used += bytes;
+    s->arena_bytes += bytes;
     it = s->arenas.emplace(stream_id, a).first;
   } else if (max_n > it->second.max_n) {
     return TG_ERR_INVALID;
@@ -457,7 +473,7 @@ tg_status tg_serve_submit(tg_server* s, const tg_request* req, uint64_t* ticket)
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop || s->failed) return TG_ERR_INVALID;
   if (tg::padded(g.n) > s->cap_gauss || (int64_t)req->cam.width * req->cam.height > s->cap_pixels ||
-      tiles_of(req->cam) > s->cap_tiles || t.footprint > s->opts.budget_bytes)
+      tiles_of(req->cam) > s->cap_tiles || t.footprint + s->arena_bytes > s->opts.budget_bytes)
     return TG_ERR_BUDGET;
   const uint64_t id = s->next_ticket++;
   s->tickets.emplace(id, t);

@@ -42,7 +42,8 @@ class Server:
     def __init__(self, device: int = 0, c: int = 32, budget_bytes: int = 64 << 30, slots: int = 3,
                  max_batch: int = 16, max_gauss_per_batch: int = 8_000_000,
                  max_keys_per_batch: int = 40_000_000, max_pixels_per_batch: int = 16 << 20,
-                 max_side: int = 1024, use_graph: bool = True, keys_per_gaussian: float = 5.0):
+                 max_side: int = 1024, use_graph: bool = True, keys_per_gaussian: float = 5.0,
+                 batch_window_us: int = 0):
         self.device = int(device)
         self.c = int(c)
         self.ctx = Context.get(self.device)
@@ -51,6 +52,7 @@ class Server:
         o.max_gauss_per_batch, o.max_keys_per_batch = int(max_gauss_per_batch), int(max_keys_per_batch)
         o.max_pixels_per_batch, o.max_side, o.c = int(max_pixels_per_batch), int(max_side), int(c)
         o.use_graph, o.keys_per_gaussian = int(bool(use_graph)), float(keys_per_gaussian)
+        o.batch_window_us = int(batch_window_us)
         self.opts = o
         self.handle = N.tg_serve_create(self.ctx.handle, o)
         self._keep = {}      # ticket -> objects that must outlive the request

@@ -41,14 +41,14 @@ def _alone(scenes_, torch):
 
 
 def _served(server, scenes_, torch, bg=None):
+    """Submit every request back to back (inputs uploaded first), wait for all."""
     from paper_2405_14866_amd.rasterize import GaussianSoA
-    outs, tickets = [], []
-    for i, sc in enumerate(scenes_):
-        g = GaussianSoA.from_scene(sc)
-        f = torch.empty((sc.c, sc.cam.height, sc.cam.width), device="cuda")
-        a = torch.empty((sc.cam.height, sc.cam.width), device="cuda")
-        tickets.append(server.submit(g, sc.cam, f, a, bg=bg, stream_id=i % 3))
-        outs.append((f, a))
+    gs = [GaussianSoA.from_scene(sc) for sc in scenes_]
+    outs = [(torch.empty((sc.c, sc.cam.height, sc.cam.width), device="cuda"),
+             torch.empty((sc.cam.height, sc.cam.width), device="cuda")) for sc in scenes_]
+    torch.cuda.synchronize()
+    tickets = [server.submit(g, sc.cam, f, a, bg=bg, stream_id=i % 3)
+               for i, (sc, g, (f, a)) in enumerate(zip(scenes_, gs, outs))]
     results = [server.wait(t) for t in tickets]
     return [(f.cpu().numpy(), a.cpu().numpy()) for f, a in outs], results
 
@@ -60,7 +60,8 @@ def test_alone_equals_in_the_mix(use_graph):
     reqs = _requests()
     alone = _alone(reqs, torch)
     srv = Server(0, c=32, slots=2, max_batch=4, max_gauss_per_batch=60000, max_keys_per_batch=600000,
-                 max_pixels_per_batch=4 * 128 * 128, max_side=128, use_graph=use_graph)
+                 max_pixels_per_batch=4 * 128 * 128, max_side=128, use_graph=use_graph,
+                 batch_window_us=200000)
     served, results = _served(srv, reqs, torch)
     srv.close()
     assert all(r.status == 0 for r in results), [r.status for r in results]
@@ -79,7 +80,7 @@ def test_served_request_matches_oracle():
     reqs = _requests(3, c=8, seed=300)
     bg = np.linspace(-1, 1, 8).astype(np.float32)
     srv = Server(0, c=8, slots=1, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=600000,
-                 max_pixels_per_batch=3 * 128 * 128, max_side=128)
+                 max_pixels_per_batch=3 * 128 * 128, max_side=128, batch_window_us=200000)
     served, results = _served(srv, reqs, torch, bg=torch.as_tensor(bg, device="cuda"))
     srv.close()
     assert results[0].batch_size == 3
@@ -100,15 +101,23 @@ def test_budget_and_capacity():
     from paper_2405_14866_amd.serve import Server
     reqs = _requests(4, seed=500)
     alone = _alone(reqs, torch)
-    # a budget that holds one request at a time: everything still completes, one per batch
-    # (bytes a request occupies in flight: padded state, estimated keys, pixel state and outputs)
+    # a budget that holds the largest request alone: everything still completes, and
+    # the requests in flight at any moment never exceed it (bytes a request occupies
+    # in flight: padded state, estimated keys, pixel state and outputs)
     fp = lambda sc: (-(-sc.n // 1024) * 1024) * 44 + (int(sc.n * 5.0) + 1024) * 20 + \
         sc.cam.width * sc.cam.height * (8 + 4 * 33)
     budget = max(fp(sc) for sc in reqs)
     srv = Server(0, c=32, slots=2, max_batch=4, max_gauss_per_batch=60000, max_keys_per_batch=600000,
-                 max_pixels_per_batch=4 * 128 * 128, max_side=128, budget_bytes=budget)
+                 max_pixels_per_batch=4 * 128 * 128, max_side=128, budget_bytes=budget,
+                 batch_window_us=100000)
     served, results = _served(srv, reqs, torch)
-    assert all(r.status == 0 and r.batch_size == 1 for r in results)
+    assert all(r.status == 0 for r in results)
+    assert sum(fp(sc) for sc in reqs) > budget            # the budget really limited the batches
+    for i, (ri, si) in enumerate(zip(results, reqs)):
+        # launched before, completed after ri's launch: in flight together with it
+        live = fp(si) + sum(fp(sj) for j, (rj, sj) in enumerate(zip(results, reqs))
+                            if j != i and rj.t_launch_ns <= ri.t_launch_ns < rj.t_done_ns)
+        assert live <= budget, (i, live, budget)
     for (fa, aa), (fs, as_) in zip(alone, served):
         assert np.array_equal(fa, fs)
     # a request larger than the budget is refused at submit
@@ -141,8 +150,10 @@ def test_key_overflow_is_readmitted_alone():
     cap = max(nk) + 16                       # every request fits alone, the batch does not
     assert sum(nk) > cap
     srv = Server(0, c=32, slots=1, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=cap,
-                 max_pixels_per_batch=3 * 128 * 128, max_side=128, keys_per_gaussian=1e-3)
+                 max_pixels_per_batch=3 * 128 * 128, max_side=128, keys_per_gaussian=1e-3,
+                 batch_window_us=200000)
     served, results = _served(srv, reqs, torch)
+    assert results[0].batch_size == 1 and results[0].retries == 1
     assert all(r.status == 0 for r in results)
     assert any(r.retries > 0 for r in results)
     for (fa, aa), (fs, as_) in zip(alone, served):
