@@ -9,7 +9,10 @@
 //            (ds_add), then one global atomic per (workgroup, touched tile);
 //   k_scan   one workgroup: exclusive scan of the tile counts -> segment
 //            offsets; the key total is checked against the frame capacity
-//            on the device (no host round trip);
+//            on the device (no host round trip); a counting sort of the
+//            tiles by descending key count (buckets of 32 keys) gives the
+//            order in which the blend's work queue hands tiles out, longest
+//            first, so that the last tiles to start are short ones;
 //   k_fill   same LDS binning, then one global atomic per (workgroup, tile)
 //            reserves a contiguous run of the tile's segment and LDS
 //            atomics hand out slots inside it; each slot receives the 64-bit
@@ -97,17 +100,27 @@ __global__ void __launch_bounds__(1024) k_count(BatchArgs a) {
 }
 
 // exclusive scan of the batch's tile counts (one workgroup of 1024 lanes)
+constexpr int ORDER_BUCKETS = 64;       // key-count buckets of the tile order
+constexpr int ORDER_SHIFT = 5;          // 32 keys per bucket
+
+__device__ __forceinline__ int order_bucket(int32_t count) {
+  return ORDER_BUCKETS - 1 - min(count >> ORDER_SHIFT, ORDER_BUCKETS - 1);
+}
+
 __global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
   __shared__ int64_t part[1024];
+  __shared__ int32_t bucket[ORDER_BUCKETS];
   const BatchHdr h = batch_hdr(a);
   const int nt = h.n_tiles;
   const int tid = threadIdx.x;
   const int per = (nt + 1023) / 1024;
   const int b = min(nt, tid * per), e = min(nt, b + per);
+  if (tid < ORDER_BUCKETS) bucket[tid] = 0;
   int64_t sum = 0;
   for (int t = b; t < e; ++t) sum += a.tile_count[t];
   part[tid] = sum;
   __syncthreads();
+  for (int t = b; t < e; ++t) atomicAdd(&bucket[order_bucket(a.tile_count[t])], 1);
   for (int off = 1; off < 1024; off <<= 1) {   // Hillis-Steele inclusive scan
     const int64_t v = tid >= off ? part[tid - off] : 0;
     __syncthreads();
@@ -128,6 +141,18 @@ __global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
     a.dev->n_keys = total;
     a.dev->overflow = over ? 1 : 0;
   }
+  if (tid == 0) {                               // bucket sizes -> first positions
+    int32_t acc = 0;
+    for (int k = 0; k < ORDER_BUCKETS; ++k) {
+      const int32_t c = bucket[k];
+      bucket[k] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  // positions inside a bucket are taken in arrival order; the blend of a
+  // tile does not depend on when it runs
+  for (int t = b; t < e; ++t) a.tile_order[atomicAdd(&bucket[order_bucket(a.tile_count[t])], 1)] = t;
 }
 
 // Scatter of one chunk's keys into the tile segments: LDS counts, one

@@ -229,10 +229,14 @@ __global__ void __launch_bounds__(256) k_render_bwd(BatchArgs a) {
   __shared__ int s_tile;
   const int tid = threadIdx.x;
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(&a.dev->bwd_queue, 1);
+    if (tid == 0) {                  // queue position -> tile, longest tiles first
+      const int k = atomicAdd(&a.dev->bwd_queue, 1);
+      s_tile = k < h.n_tiles ? a.tile_order[k] : -1;
+    }
     __syncthreads();
     const int t = s_tile;
     __syncthreads();
+    if (t < 0) break;
     const int r = req_of_tile(a, h, t);
     if (r < 0) break;
     const ReqDev& q = batch_req(a, r);

@@ -5,11 +5,11 @@
 // global tile space from a device work queue; one pixel per lane, wave w
 // owns the 8x8 quadrant (w & 1, w >> 1) of the tile.  The tile's sorted
 // Gaussian list is consumed in batches of B entries, double-buffered in LDS:
-//   * while batch b is blended, batch b+1 is fetched: its feature rows go
-//     straight from HBM into LDS with global_load_lds_dwordx4 (no VGPRs, no
-//     wait until the end of the batch), its 2D state is loaded into
-//     registers and written to LDS after the blend, and the list indices of
-//     batch b+2 are loaded the same way;
+//   * while batch b is blended, batch b+1 is fetched: its feature rows
+//     (16-byte chunks, C / 32 per lane at B = 64), its 2D state and the
+//     list indices of batch b+2 are loaded into registers and written to
+//     LDS after the blend, so the loads overlap the blend and the blend's
+//     LDS reads never wait on them;
 //   * per staged Gaussian the state is two float4: (u, v) relative to the
 //     tile origin (converted from the FP64 projection, so pixel offsets are
 //     accurate to ~1e-7 px), opacity, the exponent threshold
@@ -23,7 +23,9 @@
 //     it nothing;
 //   * the per-Gaussian body has a single wave-uniform branch for the
 //     exponential and one for the feature accumulation; the rest are
-//     selects;
+//     selects.  Each branch condition is one vector compare (the threshold
+//     test thr <= P <= 0 is a median, and an ended pixel carries +inf that
+//     is added to its exponent), so the ballot needs no mask conversion;
 //   * the feature accumulation of a step is the rank-1 update F += w f^T of
 //     the wave's 64 pixels x C channels (w: each lane's blend weight, 0 where
 //     it does not blend).  It runs on the matrix cores as C/4
@@ -47,24 +49,43 @@ constexpr float CULL_MARGIN = 0.0625f;   // px added to the alpha-support box
 constexpr int RENDER_B = 64;             // Gaussians per staged batch
 constexpr int PERSISTENT_WG = 256 * 8;   // persistent workgroups (>= resident capacity)
 
-typedef __attribute__((address_space(3))) void lds_void;
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Gather feature rows [0, nb) of the batch (global indices in sidx) into
-// LDS (row-major, C floats each) with one 16-byte LDS-DMA load per lane per
-// instruction.
+// Feature rows [0, nb) of a batch (global indices in sidx), C floats each,
+// moved in 16-byte chunks: chunk q = tid + 256 k of the batch's B * C / 4.
+// load_features issues the global loads into registers; store_features
+// writes them to LDS once the blend of the current batch is done, so the
+// loads overlap that blend and the blend's LDS reads never wait for them.
 template <int C, int B>
-__device__ __forceinline__ void dma_features(const float* __restrict__ feat, int64_t g_off,
-                                             const int32_t* sidx, float* dst, int nb, int w, int lane) {
-  constexpr int CHUNKS = C / 4;              // 16-byte chunks per row
-  constexpr int INSTR = B * CHUNKS / 64;     // wave-wide loads per batch
+struct FeatChunks {
+  static constexpr int N = (B * C / 4 + 255) / 256;   // chunks per lane (at most)
+  f4v v[N];                                           // native vectors: kept in VGPRs
+};
+
+template <int C, int B>
+__device__ __forceinline__ void load_features(const float* __restrict__ feat, int64_t g_off,
+                                              const int32_t* sidx, int nb, FeatChunks<C, B>& fc) {
+  constexpr int CHUNKS = C / 4;
 #pragma unroll
-  for (int k = w; k < INSTR; k += 4) {
-    const int q = k * 64 + lane;
+  for (int k = 0; k < FeatChunks<C, B>::N; ++k) {
+    const int q = (int)threadIdx.x + 256 * k;
     const int r = q / CHUNKS, p = q % CHUNKS;
-    const int64_t g = (int64_t)sidx[r < nb ? r : 0] - g_off;
-    const float* src = feat + g * C + 4 * p;
-    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(dst + k * 256), 16, 0, 0);
+    if (r < nb) {
+      const int64_t g = (int64_t)sidx[r] - g_off;
+      // global address space: a generic (flat) load would also count against
+      // the LDS counter and make the blend's LDS waits wait for it
+      fc.v[k] = *(const __attribute__((address_space(1))) f4v*)(feat + g * C + 4 * p);
+    }
+  }
+}
+
+template <int C, int B>
+__device__ __forceinline__ void store_features(float* dst, int nb, const FeatChunks<C, B>& fc) {
+  constexpr int CHUNKS = C / 4;
+#pragma unroll
+  for (int k = 0; k < FeatChunks<C, B>::N; ++k) {
+    const int q = (int)threadIdx.x + 256 * k;
+    if (q / CHUNKS < nb) reinterpret_cast<f4v*>(dst)[q] = fc.v[k];
   }
 }
 
@@ -145,7 +166,9 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   for (int m = 0; m < NM; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
   float T = 1.f;
   int last = -1;
-  bool done = !inside;
+  // +inf once the pixel has ended (or lies outside the image): added to the
+  // exponent before the threshold test, it fails every later test
+  float dead = inside ? 0.f : INFINITY;
   int stop_pos = -1;                  // list position that ended the pixel (COUNT only)
 
   const int nbatch = (len + B - 1) / B;
@@ -156,7 +179,8 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   }
   __syncthreads();
   if (nbatch > 0) {
-    dma_features<C, B>(feat, g_off, sh.sidx[0], sh.fe[0], min(B, len), w, lane);
+    FeatChunks<C, B> fc;
+    load_features<C, B>(feat, g_off, sh.sidx[0], min(B, len), fc);
     if (tid < B && tid < len) {
       const int g = sh.sidx[0][tid];
       float4 s0, s1;
@@ -164,7 +188,7 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
       sh.st[0][tid] = s0;
       sh.cq[0][tid] = s1;
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    store_features<C, B>(sh.fe[0], min(B, len), fc);
   }
   __syncthreads();
 
@@ -172,14 +196,15 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     const int cur = b & 1, nxt = cur ^ 1;
     const int b0 = b * B;
     const int nb = min(B, len - b0);
-    // ---- prefetch batch b+1 (features by DMA, state and next indices into registers)
+    // ---- prefetch batch b+1 (features, state and next indices into registers)
     const bool more = b + 1 < nbatch;
     const int nb1 = more ? min(B, len - b0 - B) : 0;
     double2 pxy = make_double2(0.0, 0.0);
     float4 pco = make_float4(0.f, 0.f, 0.f, 0.f);
     int pidx = 0;
+    FeatChunks<C, B> fc;
     if (more) {
-      dma_features<C, B>(feat, g_off, sh.sidx[nxt], sh.fe[nxt], nb1, w, lane);
+      load_features<C, B>(feat, g_off, sh.sidx[nxt], nb1, fc);
       if (tid < nb1) {
         const int g = sh.sidx[nxt][tid];
         pxy = a.xy[g];
@@ -194,36 +219,39 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     for (int m0 = 0; m0 < nb; m0 += 64) {
       const int jj = m0 + lane;
       const bool reach = jj < nb && (__float_as_uint(cqc[jj].w) & qbit) != 0;
-      uint64_t mask = __ballot(reach);
+      uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
+      if (!mask) continue;
       while (mask) {
-        if (__ballot(!done) == 0) break;
         const int j = m0 + (int)__builtin_ctzll(mask);
         mask &= mask - 1;
-        const float4 gs = stc[j];
-        const float4 qv = cqc[j];
+        if (__builtin_amdgcn_ballot_w64(dead == 0.f) == 0) break;
+        const float4 gs = stc[j], qv = cqc[j];
         const float dx = fpx - gs.x, dy = fpy - gs.y;
         const float P = __builtin_fmaf(dx, __builtin_fmaf(qv.x, dx, qv.y * dy), qv.z * dy * dy);
-        const bool pass = !done && P <= 0.f && P >= gs.w;
+        // thr <= P <= 0 as one median (thr is finite for every walked Gaussian)
+        const float Pm = P + dead;
         if (COUNT) ++wc.steps;
-        if (__ballot(pass) == 0) continue;
-        if (COUNT) ++wc.steps_pass;
-        const float al = fminf(0.99f, gs.z * __builtin_amdgcn_exp2f(P));
-        const bool ok = pass && al >= 1.f / 255.f;
-        const float Tn = T * (1.f - al);
-        const bool stop = ok && Tn < 1e-4f;
-        const bool blend = ok && !stop;
-        if (COUNT && stop) stop_pos = b0 + j;
-        done = done || stop;
-        const float wgt = blend ? al * T : 0.f;
-        T = blend ? Tn : T;
-        last = blend ? b0 + j : last;
-        if (COUNT && blend) ++wc.n_blend;
-        if (__ballot(blend) != 0) {
-          if (COUNT) ++wc.steps_blend;
-          float fl[NM];
-          load_slice<NM>(fec + j * C + NM * q4, fl);
+        if (__builtin_amdgcn_ballot_w64(__builtin_amdgcn_fmed3f(Pm, gs.w, 0.f) == Pm) != 0) {
+          const bool pass = __builtin_amdgcn_fmed3f(Pm, gs.w, 0.f) == Pm;
+          if (COUNT) ++wc.steps_pass;
+          const float al = fminf(0.99f, gs.z * __builtin_amdgcn_exp2f(P));
+          const bool ok = pass & (al >= 1.f / 255.f);
+          const float Tn = T * (1.f - al);
+          const bool stop = ok & (Tn < 1e-4f);
+          const bool blend = ok & !stop;
+          if (COUNT && stop) stop_pos = b0 + j;
+          dead = stop ? INFINITY : dead;
+          const float wgt = blend ? al * T : 0.f;
+          T = blend ? Tn : T;
+          last = blend ? b0 + j : last;
+          if (COUNT && blend) ++wc.n_blend;
+          if (__builtin_amdgcn_ballot_w64(wgt > 0.f) != 0) {
+            if (COUNT) ++wc.steps_blend;
+            float fl[NM];
+            load_slice<NM>(fec + j * C + NM * q4, fl);
 #pragma unroll
-          for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt, fl[m], acc[m], 0, 0, 0);
+            for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt, fl[m], acc[m], 0, 0, 0);
+          }
         }
       }
     }
@@ -235,10 +263,10 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
         sh.st[nxt][tid] = s0;
         sh.cq[nxt][tid] = s1;
       }
+      store_features<C, B>(sh.fe[nxt], nb1, fc);
       if (tid < B) sh.sidx[cur][tid] = pidx;
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(dead == 0.f) == 0) break;
   }
   if (q.bg) {                         // F += T_final bg, as one more rank-1 update
     float bl[NM];
@@ -283,19 +311,27 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   __syncthreads();                    // LDS buffers are reused by the next tile
 }
 
-template <int C, int B, bool COUNT>
+// TABLE: the batch's requests come from the device table (a replayed
+// serving batch) rather than inline (a single render); the two are separate
+// instantiations so that each keeps its own launch statistics.
+template <int C, int B, bool COUNT, bool TABLE>
 __global__ void __launch_bounds__(256) k_render(BatchArgs a) {
   if (a.dev->overflow) return;
+  if (!TABLE) a.table = nullptr;
   const BatchHdr h = batch_hdr(a);
   __shared__ RenderShared<C, B> sh;
   __shared__ int s_tile;
   const int tid = threadIdx.x;
   WorkCount wc;
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(&a.dev->tile_queue, 1);
+    if (tid == 0) {                  // queue position -> tile, longest tiles first
+      const int k = atomicAdd(&a.dev->tile_queue, 1);
+      s_tile = k < h.n_tiles ? a.tile_order[k] : -1;
+    }
     __syncthreads();
     const int t = s_tile;
     __syncthreads();
+    if (t < 0) break;
     const int r = req_of_tile(a, h, t);
     if (r < 0) break;
     const ReqDev& q = batch_req(a, r);
@@ -340,11 +376,13 @@ __global__ void k_zero_work(FrameDev* d) {
 template <int C>
 hipError_t launch_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s, bool count) {
   const int grid = grid_tiles < PERSISTENT_WG ? (grid_tiles > 0 ? grid_tiles : 1) : PERSISTENT_WG;
-  if (count) {
+  if (count) {                        // work counts: single renders only
+    if (a.table) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(1), 0, s, a.dev);
-    hipLaunchKernelGGL((k_render<C, RENDER_B, true>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_render<C, RENDER_B, true, false>), dim3(grid), dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_render<C, RENDER_B, false>), dim3(grid), dim3(256), 0, s, a);
+    if (a.table) hipLaunchKernelGGL((k_render<C, RENDER_B, false, true>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_render<C, RENDER_B, false, false>), dim3(grid), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

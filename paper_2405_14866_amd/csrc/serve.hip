@@ -77,6 +77,7 @@ struct Slot {
   int32_t* tile_count = nullptr;
   int32_t* tile_start = nullptr;
   int32_t* tile_cursor = nullptr;
+  int32_t* tile_order = nullptr;
   uint64_t* keys = nullptr;
   uint64_t* keys_tmp = nullptr;
   int32_t* sorted = nullptr;
@@ -158,6 +159,7 @@ tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
   b.tile_count = sl.tile_count;
   b.tile_start = sl.tile_start;
   b.tile_cursor = sl.tile_cursor;
+  b.tile_order = sl.tile_order;
   b.keys = sl.keys;
   b.keys_tmp = sl.keys_tmp;
   b.sorted = sl.sorted;
@@ -189,6 +191,7 @@ void free_slot(Slot& sl) {
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   if (sl.graph) (void)hipGraphDestroy(sl.graph);
   void* d[] = {sl.xy, sl.conic_o, sl.rect, sl.depth, sl.tile_count, sl.tile_start, sl.tile_cursor,
+               sl.tile_order,
                sl.keys, sl.keys_tmp, sl.sorted, sl.T_final, sl.last, sl.g2d, sl.dev, sl.table_dev,
                sl.hdr_dev};
   for (void* p : d)
@@ -208,6 +211,7 @@ bool alloc_slot(tg_server* s, Slot& sl) {
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
             dalloc(&sl.xy, g) && dalloc(&sl.conic_o, g) && dalloc(&sl.rect, g) && dalloc(&sl.depth, g) &&
             dalloc(&sl.tile_count, t) && dalloc(&sl.tile_start, t + 1) && dalloc(&sl.tile_cursor, t) &&
+            dalloc(&sl.tile_order, t) &&
             dalloc(&sl.keys, k) && dalloc(&sl.keys_tmp, k) && dalloc(&sl.sorted, k) &&
             dalloc(&sl.T_final, px) && dalloc(&sl.last, px) && dalloc(&sl.g2d, 1) && dalloc(&sl.dev, 1) &&
             dalloc(&sl.table_dev, tg::MAX_BATCH) && dalloc(&sl.hdr_dev, 1) &&

@@ -27,6 +27,7 @@ struct tg_frame {
   int32_t* tile_count = nullptr;
   int32_t* tile_start = nullptr;
   int32_t* tile_cursor = nullptr;
+  int32_t* tile_order = nullptr;
   uint64_t* keys = nullptr;
   uint64_t* keys_tmp = nullptr;
   int32_t* sorted = nullptr;
@@ -76,8 +77,8 @@ tg_status dalloc(T** p, size_t count) {
 
 void free_frame(tg_frame* f) {
   void* ptrs[] = {f->xy, f->conic_o, f->rect, f->depth, f->tile_count, f->tile_start,
-                  f->tile_cursor, f->keys, f->keys_tmp, f->sorted, f->T_final, f->last,
-                  f->g2d, f->dev};
+                  f->tile_cursor, f->tile_order, f->keys, f->keys_tmp, f->sorted, f->T_final,
+                  f->last, f->g2d, f->dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -108,6 +109,7 @@ tg::BatchArgs frame_args(tg_frame* f) {
   b.tile_count = f->tile_count;
   b.tile_start = f->tile_start;
   b.tile_cursor = f->tile_cursor;
+  b.tile_order = f->tile_order;
   b.keys = f->keys;
   b.keys_tmp = f->keys_tmp;
   b.sorted = f->sorted;
@@ -181,6 +183,7 @@ tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max
   if (st == TG_OK) st = dalloc(&f->tile_count, f->max_tiles);
   if (st == TG_OK) st = dalloc(&f->tile_start, (size_t)f->max_tiles + 1);
   if (st == TG_OK) st = dalloc(&f->tile_cursor, f->max_tiles);
+  if (st == TG_OK) st = dalloc(&f->tile_order, f->max_tiles);
   if (st == TG_OK) st = dalloc(&f->keys, max_keys);
   if (st == TG_OK) st = dalloc(&f->keys_tmp, max_keys);
   if (st == TG_OK) st = dalloc(&f->sorted, max_keys);

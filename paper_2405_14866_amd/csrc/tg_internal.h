@@ -17,6 +17,8 @@
 //                 depth   uint32   IEEE bits of the float32 view depth
 //                 g2d     float    [6][cap] backward accumulators
 //   per tile      count, start[n_tiles + 1], cursor       int32
+//                 order   int32    tiles by descending key count (the blend's
+//                                  work queue hands out the longest first)
 //   per key       keys    uint64   (depth << 32) | global index, grouped by tile
 //                 keys_tmp uint64  scratch for segments too long for LDS
 //                 sorted  int32    global index, per tile in (depth, index) order
@@ -107,6 +109,7 @@ struct BatchArgs {
   int32_t* tile_count;
   int32_t* tile_start;
   int32_t* tile_cursor;
+  int32_t* tile_order;
   uint64_t* keys;
   uint64_t* keys_tmp;
   int32_t* sorted;
