@@ -1,111 +1,97 @@
 // render_bwd.hip -- adjoint of the rasterizer (gfx950).  §4.2 trains the
 // encoder and decoder through R_G, so R_G must be differentiable.
 //
-// k_render_bwd: one 256-lane workgroup per 16x16 tile (same pixel layout as
-// the forward).  Nothing per (pixel, Gaussian) is stored by the forward;
-// each pixel starts from its final transmittance T_final and the list
-// position of its last blended Gaussian, and walks its list backwards,
-// re-deciding skip / blend with exactly the forward's float operations and
-// recovering T_i = T_{i+1} / (1 - alpha_i).  With S_i = sum_{j>i} alpha_j
-// T_j f_j + T_final bg (tracked as the scalar <dL/dF, S_i>):
-//   dL/dalpha_i = T_i <g, f_i> - <g, S_i> / (1 - alpha_i)
-//                 + dL/dA_out T_final / (1 - alpha_i)
-//   dL/df_i    += alpha_i T_i g
-// and, unless alpha was clamped at 0.99, dL/dP = alpha dL/dalpha with
-// P = -(A dx^2 + C dy^2)/2 - B dx dy, giving the 2D gradients (u, v, A, B,
-// C, opacity).  Per Gaussian the 64 lanes' contributions are summed by a
-// transposing butterfly (each exchange halves the values a lane holds, so
-// V values cost about V shuffles instead of 6 V), the 4 waves are summed in
-// LDS and the tile's total is added to the per-Gaussian accumulators with
-// one float atomic per value.
+// k_render_bwd: persistent 256-lane workgroups over the tiles (longest
+// first), the forward's pixel layout (wave w owns the 8x8 quadrant
+// (w & 1, w >> 1)).  Nothing per (pixel, Gaussian) is stored by the
+// forward: each pixel starts from its final transmittance T_final and the
+// list position of its last blended Gaussian and walks its list backwards,
+// re-deciding skip / blend with the forward's own float operations (shared
+// code) and recovering T_i = T_{i+1} / (1 - alpha_i).  With
+// S_i = sum_{j>i} alpha_j T_j f_j + T_final bg (kept as <g, S_i>, g = dL/dF
+// of the pixel):
+//   dL/dalpha_i = T_i <g, f_i> - (<g, S_i> - dL/dA_out T_final) / (1 - alpha_i)
+//   dL/df_i    += w_i g,  w_i = alpha_i T_i
+//   dL/dP_i     = alpha_i dL/dalpha_i (0 where alpha is clamped at 0.99)
+// and the 2D gradients of (u, v, conic A, B, C, opacity) follow from dL/dP
+// and the pixel offset d = p - (u, v).
+//
+// The per-Gaussian sums over a wave's 64 pixels are dense contractions and
+// run on the matrix cores.  Each wave walks the Gaussians that reach its
+// quadrant (the forward's conservative quadrant test) in groups of 16; the
+// walk writes each pixel's w_i and dL/dP_i into LDS, then
+//   dL/df[i][c]  = sum_p w_i(p) g(p)[c]            (16 x C x 64)
+//   M[i][k]      = sum_p dL/dP_i(p) phi_k(p)         (16 x 6 x 64)
+// are v_mfma_f32_16x16x4_f32 products with the pixels as the reduction
+// index; phi = (1, x, y, x^2, xy, y^2) of the pixel centre relative to the
+// wave's quadrant centre, from which the six 2D gradient sums are assembled
+// exactly (sum dP dx = M_x - u M_1, ...).  Each wave adds its group's sums to the
+// per-Gaussian accumulators with one float atomic per value.
 //
 // k_project_bwd: one lane per Gaussian, FP64 chain rule from the 2D
 // gradients to the raw parameters (mean, log-scale, unnormalised
 // quaternion, opacity logit) through the EWA projection.
-#include "tg_internal.h"
+#include "blend_common.h"
 
 namespace tg {
 namespace {
 
-constexpr float LOG2E = 1.4426950408889634f;
+constexpr int BWD_B = 64;      // Gaussians per staged batch
+constexpr int GROUP = 16;      // Gaussians per matrix-core reduction
 
-// Sum V values over the 64 lanes.  On return v[0] of every lane holds the
-// full sum of value index reduce_index<V>(lane).
-template <int V>
-__device__ __forceinline__ void transpose_reduce(float (&v)[V], int lane) {
-  int o = 32;
-#pragma unroll
-  for (int half = V / 2; half >= 1; half >>= 1) {
-    if (o >= 1) {
-      const bool up = (lane & o) != 0;
-#pragma unroll
-      for (int i = 0; i < half; ++i) {
-        const float send = up ? v[i] : v[i + half];
-        const float keep = up ? v[i + half] : v[i];
-        v[i] = keep + __shfl_xor(send, o, 64);
-      }
-      o >>= 1;
-    }
-  }
-  for (; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
-}
-
-template <int V>
-__device__ __forceinline__ int reduce_index(int lane) {
-  int idx = 0, o = 32;
-  for (int half = V / 2; half >= 1 && o >= 1; half >>= 1, o >>= 1)
-    if (lane & o) idx += half;
-  return idx;
-}
-
-// lanes whose bits below the butterfly's split bits are zero hold unique results
-template <int V>
-__device__ __forceinline__ bool reduce_writer(int lane) {
-  int bits = 0;
-  for (int x = V; x > 1; x >>= 1) ++bits;
-  if (bits >= 6) return true;
-  const int low = (1 << (6 - bits)) - 1;
-  return (lane & low) == 0;
-}
-
-template <int C, int BATCH>
+template <int C>
 struct BwdShared {
-  float4 sg[BATCH];     // u, v (tile-local), opacity, log2 threshold
-  float4 sq[BATCH];     // scaled conic (as in the forward)
-  float4 sc[BATCH];     // unscaled conic A, B, C
-  int32_t sidx[BATCH];
-  __align__(16) float sf[BATCH][C + 4];
-  float r2d[4][BATCH][8];
-  float rft[4][BATCH][C];
-  int32_t rflag[4][BATCH];
+  float4 st[BWD_B];            // as in the forward
+  float4 cq[BWD_B];
+  float4 cn[BWD_B];            // unscaled conic A, B, C and opacity
+  int32_t sidx[BWD_B];
+  __align__(16) float fe[BWD_B * C];
+  int32_t wl[4][BWD_B];        // per wave: reaching batch entries, last first
+  // per wave, row i of the group: pixel values in k-block order, p = 4 kb + q
+  // stored at q * 16 + kb (so one lane's 16 A operands are contiguous)
+  __align__(16) float wa[4][GROUP * 64];
+  __align__(16) float dp[4][GROUP * 64];
+  float mom[4][GROUP][8];
   int32_t smax;
 };
 
-template <int C, int BATCH>
+__device__ __forceinline__ int perm64(int p) { return (p & 3) * 16 + (p >> 2); }
+
+typedef __attribute__((address_space(1))) float gfloat;
+
+// float atomic add on a global-memory address (no-return form; the generic
+// form would be a flat atomic that also counts against the LDS counter)
+__device__ __forceinline__ void atomic_add_global(float* p, float v) {
+  (void)__builtin_amdgcn_global_atomic_fadd_f32((gfloat*)p, v);
+}
+
+template <int C>
 __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, int gtile, int tx, int ty,
-                                         BwdShared<C, BATCH>& sh) {
+                                         BwdShared<C>& sh) {
+  constexpr int NB = (C + 15) / 16;           // 16-channel blocks of dL/df
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int lx = ((w & 1) << 3) | (lane & 7);
-  const int ly = ((w >> 1) << 3) | (lane >> 3);
+  const int ql = lane >> 4, l16 = lane & 15;  // MFMA operand row / column of this lane
+  const int qx0 = (w & 1) << 3, qy0 = (w >> 1) << 3;
+  const int lx = qx0 | (lane & 7), ly = qy0 | (lane >> 3);
   const int W = q.cam.W, H = q.cam.H;
   const int px = tx * TILE + lx, py = ty * TILE + ly;
   const bool inside = px < W && py < H;
   const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
   const double ox = (double)(tx * TILE), oy = (double)(ty * TILE);
   const int s = a.tile_start[gtile];
-  auto& sg = sh.sg; auto& sq = sh.sq; auto& sc = sh.sc; auto& sidx = sh.sidx; auto& sf = sh.sf;
-  auto& r2d = sh.r2d; auto& rft = sh.rft; auto& rflag = sh.rflag; auto& smax = sh.smax;
-
+  const uint32_t qbit = 1u << w;
   const size_t HW = (size_t)W * H;
-  const size_t pix = inside ? (size_t)py * W + px : 0;
+
+  // ---- per-pixel state
   float g[C];
-  float T = 1.f, gA = 0.f, sgS = 0.f, Tfin = 1.f;
+  float T = 1.f, sgS = 0.f, gAT = 0.f;
   int last = -1;
   if (inside) {
-    Tfin = q.T_final[pix];
+    const size_t pix = (size_t)py * W + px;
+    const float Tfin = q.T_final[pix];
     T = Tfin;
     last = q.last[pix];
-    gA = q.d_alpha ? q.d_alpha[pix] : 0.f;
+    gAT = (q.d_alpha ? q.d_alpha[pix] : 0.f) * Tfin;
     float gb = 0.f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -117,115 +103,176 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
 #pragma unroll
     for (int c = 0; c < C; ++c) g[c] = 0.f;
   }
-  if (tid == 0) smax = -1;
-  for (int k = tid; k < 4 * BATCH; k += 256) (&rflag[0][0])[k] = 0;
-  __syncthreads();
-  if (last >= 0) atomicMax(&smax, last);
-  __syncthreads();
-  const int maxlast = smax;
-  if (maxlast < 0) {
-    __syncthreads();                 // smax is rewritten by the next tile
-    return;
+  // ---- matrix-core operands fixed for the tile.  B of the dL/df product:
+  // lane (ql, l16) of k-block kb holds g[c = 16 nb + l16] of wave pixel
+  // p = 4 kb + ql; B of the moment product holds phi_l16 of that pixel.
+  float gB[NB][16], phB[16];
+#pragma unroll
+  for (int kb = 0; kb < 16; ++kb) {
+    const int p = 4 * kb + ql;
+    const int plx = qx0 | (p & 7), ply = qy0 | (p >> 3);
+    const int ppx = tx * TILE + plx, ppy = ty * TILE + ply;
+    const bool pin = ppx < W && ppy < H;
+    const size_t ppix = pin ? (size_t)ppy * W + ppx : 0;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = 16 * nb + l16;
+      gB[nb][kb] = (pin && c < C) ? q.d_img[c * HW + ppix] : 0.f;
+    }
+    const float x = (float)(plx - qx0) - 3.5f, y = (float)(ply - qy0) - 3.5f;
+    float ph = 0.f;
+    ph = l16 == 0 ? 1.f : ph;
+    ph = l16 == 1 ? x : ph;
+    ph = l16 == 2 ? y : ph;
+    ph = l16 == 3 ? x * x : ph;
+    ph = l16 == 4 ? x * y : ph;
+    ph = l16 == 5 ? y * y : ph;
+    phB[kb] = ph;
   }
-  const float gAT = gA * Tfin;
+  // ---- the list range any pixel of the tile (of this wave) still needs
+  int wmax = last;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+  if (tid == 0) sh.smax = -1;
+  __syncthreads();
+  if (lane == 0) atomicMax(&sh.smax, wmax);
+  __syncthreads();
+  const int tmax = sh.smax;
 
-  for (int b = maxlast / BATCH; b >= 0; --b) {
-    const int b0 = b * BATCH;
-    const int nb = min(BATCH, maxlast + 1 - b0);
+  float* const d_feat = q.d_feat;
+  const int64_t g_off = q.g_off;
+  for (int b = tmax >= 0 ? tmax / BWD_B : -1; b >= 0; --b) {
+    const int b0 = b * BWD_B;
+    const int nb = min(BWD_B, tmax + 1 - b0);
+    __syncthreads();                          // the previous batch is done with the buffers
     if (tid < nb) {
       const int gi = a.sorted[s + b0 + tid];
-      const double2 xy = a.xy[gi];
       const float4 co = a.conic_o[gi];
-      const float o = co.w;
-      const float thr = o > 0.f ? -log2f(255.f * o) : INFINITY;
-      sg[tid] = make_float4((float)(xy.x - ox), (float)(xy.y - oy), o, thr);
-      sq[tid] = make_float4(-0.5f * LOG2E * co.x, -LOG2E * co.y, -0.5f * LOG2E * co.z, 0.f);
-      sc[tid] = make_float4(co.x, co.y, co.z, 0.f);
-      sidx[tid] = gi;
-      const float4* fr = reinterpret_cast<const float4*>(q.feat + (size_t)(gi - q.g_off) * C);
-#pragma unroll
-      for (int q = 0; q < C / 4; ++q) *reinterpret_cast<float4*>(&sf[tid][4 * q]) = fr[q];
+      float4 s0, s1;
+      make_state(a.xy[gi], co, ox, oy, s0, s1);
+      sh.st[tid] = s0;
+      sh.cq[tid] = s1;
+      sh.cn[tid] = co;
+      sh.sidx[tid] = gi;
+    }
+    for (int k = tid; k < nb * (C / 4); k += 256) {
+      const int r = k / (C / 4), c4 = k % (C / 4);
+      const int gi = a.sorted[s + b0 + r];
+      reinterpret_cast<float4*>(sh.fe)[k] =
+          reinterpret_cast<const float4*>(q.feat + (size_t)(gi - g_off) * C)[c4];
     }
     __syncthreads();
-    for (int j = nb - 1; j >= 0; --j) {
-      const int pos = b0 + j;
-      const float4 gs = sg[j];
-      const float4 q = sq[j];
-      const float dx = fpx - gs.x, dy = fpy - gs.y;
-      const float P = __builtin_fmaf(dx, __builtin_fmaf(q.x, dx, q.y * dy), q.z * dy * dy);
-      bool contrib = false;
-      float al = 0.f, G = 0.f;
-      if (pos <= last && P <= 0.f && P >= gs.w) {
-        G = __builtin_amdgcn_exp2f(P);
-        al = fminf(0.99f, gs.z * G);
-        contrib = al >= 1.f / 255.f;
-      }
-      if (__ballot(contrib) == 0) continue;
-      float v2[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      float vf[C];
-      if (contrib) {
-        const float oma = 1.f - al;
-        const float Ti = T / oma;
-        float fg = 0.f;
+    if (b0 > wmax) continue;                  // no pixel of this quadrant reaches this batch
+    // reaching entries of the batch, last first
+    const bool reach = lane < nb && (__float_as_uint(sh.cq[lane].w) & qbit) != 0 && b0 + lane <= wmax;
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
+    const int cnt = __builtin_popcountll(mask);
+    if (reach) sh.wl[w][__builtin_popcountll(lane == 63 ? 0ull : mask >> (lane + 1))] = lane;
+    __builtin_amdgcn_wave_barrier();
+    for (int g0 = 0; g0 < cnt; g0 += GROUP) {
+      const int n = min(GROUP, cnt - g0);
+      uint32_t cmask = 0;                     // rows of the group some pixel blends
+      for (int i = 0; i < n; ++i) {
+        const int j = sh.wl[w][g0 + i];
+        const int pos = b0 + j;
+        const float4 gs = sh.st[j], qv = sh.cq[j];
+        const float P = exponent(gs, qv, fpx, fpy);
+        const bool ok = pos <= last && passes(P, gs.w);
+        float wv = 0.f, dv = 0.f;
+        if (__builtin_amdgcn_ballot_w64(ok) != 0) {
+          const float G = __builtin_amdgcn_exp2f(P);
+          const float al = fminf(0.99f, gs.z * G);
+          const bool contrib = ok & (al >= 1.f / 255.f);
+          if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
+            cmask |= 1u << i;
+            const float* fr = sh.fe + j * C;
+            float fg = 0.f;
 #pragma unroll
-        for (int c = 0; c < C; ++c) fg = __builtin_fmaf(sf[j][c], g[c], fg);
-        const float dLda = Ti * fg + (gAT - sgS) / oma;
-        const float wgt = al * Ti;
-        sgS = __builtin_fmaf(wgt, fg, sgS);
-#pragma unroll
-        for (int c = 0; c < C; ++c) vf[c] = wgt * g[c];
-        if (gs.z * G <= 0.99f) {
-          const float4 cn = sc[j];
-          // dx, dy here are pixel - mean; P = -(A dx^2 + C dy^2)/2 - B dx dy
-          const float dP = dLda * al;
-          v2[0] = dP * (cn.x * dx + cn.y * dy);
-          v2[1] = dP * (cn.z * dy + cn.y * dx);
-          v2[2] = -0.5f * dP * dx * dx;
-          v2[3] = -dP * dx * dy;
-          v2[4] = -0.5f * dP * dy * dy;
-          v2[5] = dLda * G;
+            for (int c = 0; c < C; ++c) fg = __builtin_fmaf(fr[c], g[c], fg);
+            // T_i = T_{i+1} / (1 - alpha_i) with a correctly rounded division:
+            // the recursion runs over the whole list, an approximate
+            // reciprocal would let its error grow with the list length
+            const float oma = 1.f - al;
+            const float Ti = T / oma;
+            const float dLda = Ti * fg + (gAT - sgS) * __builtin_amdgcn_rcpf(oma);
+            const float wgt = al * Ti;
+            wv = contrib ? wgt : 0.f;
+            dv = contrib && gs.z * G <= 0.99f ? dLda * al : 0.f;
+            sgS = contrib ? __builtin_fmaf(wgt, fg, sgS) : sgS;
+            T = contrib ? Ti : T;
+          }
         }
-        T = Ti;
-      } else {
-#pragma unroll
-        for (int c = 0; c < C; ++c) vf[c] = 0.f;
+        sh.wa[w][i * 64 + perm64(lane)] = wv;
+        sh.dp[w][i * 64 + perm64(lane)] = dv;
       }
-      transpose_reduce<8>(v2, lane);
-      transpose_reduce<C>(vf, lane);
-      if (reduce_writer<8>(lane)) r2d[w][j][reduce_index<8>(lane)] = v2[0];
-      if (reduce_writer<C>(lane)) rft[w][j][reduce_index<C>(lane)] = vf[0];
-      if (lane == 0) rflag[w][j] = 1;
-    }
-    __syncthreads();
-    // sum the waves and add the tile's share to the per-Gaussian totals
-    for (int k = tid; k < nb * (6 + C); k += 256) {
-      const int j = k / (6 + C), v = k % (6 + C);
-      float sum = 0.f;
-      bool any = false;
+      if (cmask == 0) continue;
+      __builtin_amdgcn_wave_barrier();
+      // ---- sums over the wave's pixels on the matrix cores
+      f4v accF[NB], accM = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ww = 0; ww < 4; ++ww) {
-        if (rflag[ww][j]) {
-          any = true;
-          sum += v < 6 ? r2d[ww][j][v] : rft[ww][j][v - 6];
+      for (int nb2 = 0; nb2 < NB; ++nb2) accF[nb2] = f4v{0.f, 0.f, 0.f, 0.f};
+      const f4v* wrow = reinterpret_cast<const f4v*>(&sh.wa[w][l16 * 64 + ql * 16]);
+      const f4v* drow = reinterpret_cast<const f4v*>(&sh.dp[w][l16 * 64 + ql * 16]);
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const f4v av = wrow[k4], dvv = drow[k4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int kb = 4 * k4 + e;
+#pragma unroll
+          for (int nb2 = 0; nb2 < NB; ++nb2)
+            accF[nb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], gB[nb2][kb], accF[nb2], 0, 0, 0);
+          accM = __builtin_amdgcn_mfma_f32_16x16x4f32(dvv[e], phB[kb], accM, 0, 0, 0);
         }
       }
-      if (any) {
-        const int gi = sidx[j];
-        if (v < 6) atomicAdd(&a.g2d[(int64_t)v * a.g_cap + gi], sum);
-        else atomicAdd(&q.d_feat[(size_t)(gi - q.g_off) * C + (v - 6)], sum);
+      // accF[nb][r] = dL/df[row 4 ql + r][16 nb + l16]; accM[r] = M[row 4 ql + r][l16]
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * ql + r;
+        if (l16 < 6) sh.mom[w][i][l16] = accM[r];
+        if (i < n && ((cmask >> i) & 1u)) {
+          const int gi = sh.sidx[sh.wl[w][g0 + i]];
+          float* dst = d_feat + (size_t)(gi - g_off) * C;
+#pragma unroll
+          for (int nb2 = 0; nb2 < NB; ++nb2) {
+            const int c = 16 * nb2 + l16;
+            if (c < C) atomic_add_global(dst + c, accF[nb2][r]);
+          }
+        }
       }
+      __builtin_amdgcn_wave_barrier();
+      if (lane < n && ((cmask >> lane) & 1u)) {
+        const int j = sh.wl[w][g0 + lane];
+        const int gi = sh.sidx[j];
+        const float4 gs = sh.st[j], cn = sh.cn[j];
+        const float* m = sh.mom[w][lane];
+        // pixel offsets d = p - (u, v) with p and (u, v) relative to the quadrant centre
+        const float u = gs.x - (float)(qx0 + 4), v = gs.y - (float)(qy0 + 4);
+        const float m1 = m[0], mx = m[1], my = m[2], mxx = m[3], mxy = m[4], myy = m[5];
+        const float sdx = mx - u * m1, sdy = my - v * m1;
+        const float sdxx = mxx - 2.f * u * mx + u * u * m1;
+        const float sdxy = mxy - u * my - v * mx + u * v * m1;
+        const float sdyy = myy - 2.f * v * my + v * v * m1;
+        float* g2 = a.g2d + gi;
+        const int64_t gc = a.g_cap;
+        atomic_add_global(g2, cn.x * sdx + cn.y * sdy);
+        atomic_add_global(g2 + gc, cn.z * sdy + cn.y * sdx);
+        atomic_add_global(g2 + 2 * gc, -0.5f * sdxx);
+        atomic_add_global(g2 + 3 * gc, -sdxy);
+        atomic_add_global(g2 + 4 * gc, -0.5f * sdyy);
+        atomic_add_global(g2 + 5 * gc, m1 / gs.z);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-    for (int k = tid; k < 4 * BATCH; k += 256) (&rflag[0][0])[k] = 0;
-    __syncthreads();
   }
+  __syncthreads();                            // smax and the buffers are reused by the next tile
 }
 
-template <int C, int BATCH>
+template <int C>
 __global__ void __launch_bounds__(256) k_render_bwd(BatchArgs a) {
   if (a.dev->overflow) return;
   const BatchHdr h = batch_hdr(a);
-  __shared__ BwdShared<C, BATCH> sh;
+  __shared__ BwdShared<C> sh;
   __shared__ int s_tile;
   const int tid = threadIdx.x;
   for (;;) {
@@ -241,7 +288,7 @@ __global__ void __launch_bounds__(256) k_render_bwd(BatchArgs a) {
     if (r < 0) break;
     const ReqDev& q = batch_req(a, r);
     const int lt = t - q.tile_off;
-    bwd_tile<C, BATCH>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, sh);
+    bwd_tile<C>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, sh);
   }
   if (tid == 0 && atomicAdd(&a.dev->bwd_done, 1) == (int)gridDim.x - 1) {
     atomicExch(&a.dev->bwd_queue, 0);
@@ -265,9 +312,8 @@ constexpr int BWD_PERSISTENT_WG = 256 * 6;
 
 template <int C>
 hipError_t launch_bwd_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s) {
-  constexpr int BATCH = 32;
   const int grid = grid_tiles < BWD_PERSISTENT_WG ? (grid_tiles > 0 ? grid_tiles : 1) : BWD_PERSISTENT_WG;
-  hipLaunchKernelGGL((k_render_bwd<C, BATCH>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_render_bwd<C>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -39,17 +39,14 @@
 // Per pixel: P = -d^T conic d / 2; skip when P > 0 or when P is below the
 // opacity threshold (alpha < 1/255); alpha = min(0.99, o e^P); a Gaussian
 // that would take T below 1e-4 ends the pixel without being blended.
-#include "tg_internal.h"
+#include "blend_common.h"
 
 namespace tg {
 namespace {
 
-constexpr float LOG2E = 1.4426950408889634f;
-constexpr float CULL_MARGIN = 0.0625f;   // px added to the alpha-support box
 constexpr int RENDER_B = 64;             // Gaussians per staged batch
 constexpr int PERSISTENT_WG = 256 * 8;   // persistent workgroups (>= resident capacity)
 
-typedef float f4v __attribute__((ext_vector_type(4)));
 
 // Feature rows [0, nb) of a batch (global indices in sidx), C floats each,
 // moved in 16-byte chunks: chunk q = tid + 256 k of the batch's B * C / 4.
@@ -102,31 +99,6 @@ __device__ __forceinline__ void load_slice(const float* p, float (&fl)[NM]) {
     const float2 v = *reinterpret_cast<const float2*>(p);
     fl[0] = v.x; fl[1] = v.y;
   }
-}
-
-// 2D state of one staged Gaussian, from the projection of step 1.
-__device__ __forceinline__ void make_state(double2 xy, float4 co, double ox, double oy,
-                                           float4& st, float4& cq) {
-  const float u = (float)(xy.x - ox), v = (float)(xy.y - oy);
-  const float o = co.w;
-  float thr = INFINITY;
-  uint32_t mask = 0;
-  if (o * 255.f >= 1.f) {
-    thr = -log2f(255.f * o);
-    // alpha >= 1/255  <=>  d^T Q d <= rho = 2 ln(255 o); box of that ellipse
-    const float rho = 2.f * logf(255.f * o);
-    const float det = co.x * co.z - co.y * co.y;
-    const float ex = sqrtf(fmaxf(rho * co.z / det, 0.f)) + CULL_MARGIN;
-    const float ey = sqrtf(fmaxf(rho * co.x / det, 0.f)) + CULL_MARGIN;
-#pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {
-      const float x0 = (float)((qd & 1) * 8) + 0.5f, y0 = (float)((qd >> 1) * 8) + 0.5f;
-      const bool hit = (u + ex >= x0) && (u - ex <= x0 + 7.f) && (v + ey >= y0) && (v - ey <= y0 + 7.f);
-      mask |= hit ? (1u << qd) : 0u;
-    }
-  }
-  st = make_float4(u, v, o, thr);
-  cq = make_float4(-0.5f * LOG2E * co.x, -LOG2E * co.y, -0.5f * LOG2E * co.z, __uint_as_float(mask));
 }
 
 struct WorkCount {
@@ -226,15 +198,13 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
         mask &= mask - 1;
         if (__builtin_amdgcn_ballot_w64(dead == 0.f) == 0) break;
         const float4 gs = stc[j], qv = cqc[j];
-        const float dx = fpx - gs.x, dy = fpy - gs.y;
-        const float P = __builtin_fmaf(dx, __builtin_fmaf(qv.x, dx, qv.y * dy), qv.z * dy * dy);
-        // thr <= P <= 0 as one median (thr is finite for every walked Gaussian)
+        const float P = exponent(gs, qv, fpx, fpy);
         const float Pm = P + dead;
         if (COUNT) ++wc.steps;
-        if (__builtin_amdgcn_ballot_w64(__builtin_amdgcn_fmed3f(Pm, gs.w, 0.f) == Pm) != 0) {
-          const bool pass = __builtin_amdgcn_fmed3f(Pm, gs.w, 0.f) == Pm;
+        if (__builtin_amdgcn_ballot_w64(passes(Pm, gs.w)) != 0) {
+          const bool pass = passes(Pm, gs.w);
           if (COUNT) ++wc.steps_pass;
-          const float al = fminf(0.99f, gs.z * __builtin_amdgcn_exp2f(P));
+          const float al = blend_alpha(gs.z, P);
           const bool ok = pass & (al >= 1.f / 255.f);
           const float Tn = T * (1.f - al);
           const bool stop = ok & (Tn < 1e-4f);

@@ -269,7 +269,7 @@ def make_cfg4_request(req_id: int, base_seed: int = 40000):
     """One serving request: N ~ U{100k..1M} Gaussians from the small-scene
     generator on a ceil(sqrt(N)) grid, C = 32, target resolution drawn from
     {512, 768, 1024}, target pose jittered +-10 deg yaw / +-5 deg pitch about
-    frontal.  Returns (scene, stream_id)."""
+    frontal."""
     rng = np.random.default_rng(base_seed + req_id)
     n = int(rng.integers(100_000, 1_000_001))
     res = int(rng.choice([512, 768, 1024]))

@@ -47,6 +47,25 @@ def compare_grads(gpu, ref, skip, rel=1e-4):
     return worst
 
 
+def compare_grads_loose(gpu, ref, only, rel=2e-2):
+    """The Gaussians a near-threshold pixel walks over, against a looser bar:
+    a decision that flips at alpha = 1/255 or T = 1e-4 changes that pixel's
+    transmittance by well under 1 %, and the Gaussian's gradient sums many
+    pixels."""
+    floor = 1e-9 * max(np.sqrt(np.mean(np.asarray(ref[k], np.float64) ** 2)) for k in GROUPS)
+    for k in GROUPS:
+        a = np.asarray(gpu[k], np.float64)
+        b = np.asarray(ref[k], np.float64)
+        if a.ndim == 2 and k != "feat":
+            a, b = a[:, only], b[:, only]
+        else:
+            a, b = a[only], b[only]
+        # same rms floor as compare_grads (a group that vanishes identically)
+        rms = max(np.sqrt(np.mean(np.asarray(ref[k], np.float64) ** 2)), floor) + 1e-30
+        err = np.abs(a - b) / (np.abs(b) + rms)
+        assert err.size == 0 or err.max() <= rel, (k, float(err.max()))
+
+
 def _run(scene, dF, dA=None, bg=None):
     torch = torch_cuda()
     gpu, rast, g = gpu_render(scene, bg=bg, lists=False)
@@ -120,3 +139,18 @@ def test_autograd_function_matches_oracle(cfg1):
                quat=quats.grad.cpu().numpy().T, opacity_logit=logits.grad.cpu().numpy(),
                feat=feats.grad.cpu().numpy())
     compare_grads(got, ref, skip)
+
+
+@pytest.mark.parametrize("which", ["realistic", "scaled_grid"])
+def test_full_size_backward(which):
+    """The adjoint at full size in the benchmark's launch configuration: the
+    realistic frame (~471k Gaussians, C = 32, 1024^2) and the small-scene
+    generator scaled to a 1024^2 grid (1,048,576 Gaussians, C = 32, 1024^2),
+    dL/dF ~ N(0, 1).  Every gradient of every Gaussian is compared; those
+    walked by a near-threshold pixel against the looser bar."""
+    sc = scenes.make_cfg2() if which == "realistic" else scenes.make_cfg3_scaled()
+    dF = scenes.make_cfg3_upstream(3, sc.c, sc.cam.height, sc.cam.width)
+    out, ref, skip = _run(sc, dF)
+    worst = compare_grads(out, ref, skip)
+    compare_grads_loose(out, ref, skip)
+    print(which, "worst", worst, "near-threshold Gaussians", len(skip), "of", sc.n)

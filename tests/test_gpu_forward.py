@@ -239,3 +239,17 @@ def test_work_counts_match_oracle():
     assert abs(n_eval - e_ref) <= 2000 * nflag and abs(n_blend - b_ref) <= 2 * nflag
     assert steps_blend <= steps_pass <= steps
     print("work", n_eval, n_blend, steps, steps_pass, steps_blend)
+
+
+def test_stress_frame_full_resolution():
+    """The stress workload (the realistic generator at 2048^2 per view:
+    ~7.55M Gaussians, ~17.8M keys, tiles of up to ~5.8k keys that take the
+    large-segment sort, 2048^2 target): every tile list bit for bit and every
+    pixel against the oracle."""
+    sc = scenes.make_cfg5()
+    gpu, _, _ = gpu_render(sc)
+    ora = oracle.Oracle(sc)
+    compare_lists(gpu, ora)
+    rep = compare_forward(gpu, ora)
+    print("stress", rep, "keys", gpu["n_keys"])
+    assert rep["excluded"] == 0

@@ -206,3 +206,29 @@ def test_stream_arena_is_resident_and_budgeted():
     with pytest.raises(N.TgError):
         srv.stream_arena(4, 1 << 20)         # would exceed the 4 MiB budget
     srv.close()
+
+
+def test_serving_requests_at_full_size():
+    """Six requests of the serving workload (100k..1M Gaussians each, C = 32,
+    512^2..1024^2 targets) batched by the server: each equals its plain
+    render bit for bit, and the smallest matches the oracle."""
+    torch = torch_cuda()
+    from paper_2405_14866_amd.serve import Server
+    reqs = [scenes.make_cfg4_request(i) for i in range(6)]
+    alone = _alone(reqs, torch)
+    n_sum = sum(sc.n for sc in reqs)
+    srv = Server(0, c=32, slots=2, max_batch=4, max_gauss_per_batch=n_sum + 8 * 1024,
+                 max_keys_per_batch=int(4.0 * n_sum), max_pixels_per_batch=4 * 1024 * 1024,
+                 max_side=1024, keys_per_gaussian=2.5, batch_window_us=300000)
+    served, results = _served(srv, reqs, torch)
+    srv.close()
+    assert all(r.status == 0 for r in results), [r.status for r in results]
+    assert max(r.batch_size for r in results) > 1
+    for (fa, aa), (fs, as_) in zip(alone, served):
+        assert np.array_equal(fa, fs) and np.array_equal(aa, as_)
+    k = int(np.argmin([sc.n for sc in reqs]))
+    ora = oracle.Oracle(reqs[k])
+    f, a = served[k]
+    rep = compare_forward(dict(feat=f, alpha=a, last=np.zeros_like(a, dtype=np.int32)), ora,
+                          check_last=False)
+    print("served request", k, reqs[k].n, rep)
