@@ -2,14 +2,22 @@
 // of C-channel latent features (gfx950).
 //
 // Persistent workgroups of 256 lanes (4 wave64) take tiles of the batch's
-// global tile space from a device work queue; one pixel per lane, wave w
-// owns the 8x8 quadrant (w & 1, w >> 1) of the tile.  The tile's sorted
-// Gaussian list is consumed in batches of B entries, double-buffered in LDS:
-//   * while batch b is blended, batch b+1 is fetched: its feature rows
-//     (16-byte chunks, C / 32 per lane at B = 64), its 2D state and the
-//     list indices of batch b+2 are loaded into registers and written to
-//     LDS after the blend, so the loads overlap the blend and the blend's
-//     LDS reads never wait on them;
+// global tile space from a device work queue, longest tiles first; one
+// pixel per lane, wave w owns the 8x8 quadrant (w & 1, w >> 1) of the tile.
+// The tile's sorted Gaussian list is consumed in batches of B entries,
+// double-buffered in LDS:
+//   * while batch b is blended, batch b+1 is fetched by LDS DMA
+//     (global_load_lds_dwordx4): its feature rows as 16-byte chunks over
+//     the four waves, its raw FP64 2D mean and conic (one 16-byte load per
+//     entry), straight into the other buffer without passing through
+//     VGPRs; the list indices of batch b+2 come into a register.  The two
+//     buffers are separate LDS objects and the batch loop is unrolled by
+//     two, so the compiler can tell the DMA target from the buffer being
+//     walked and the walk never waits for the DMA; each wave waits for its
+//     own DMA before the barrier that ends the batch;
+//   * the kernel asks for six waves per SIMD: latency, not issue, bounds the
+//     walk, and the few loop-invariant values that do not fit are kept in
+//     scratch outside the walk;
 //   * per staged Gaussian the state is two float4: (u, v) relative to the
 //     tile origin (converted from the FP64 projection, so pixel offsets are
 //     accurate to ~1e-7 px), opacity, the exponent threshold
@@ -48,44 +56,6 @@ constexpr int RENDER_B = 64;             // Gaussians per staged batch
 constexpr int PERSISTENT_WG = 256 * 8;   // persistent workgroups (>= resident capacity)
 
 
-// Feature rows [0, nb) of a batch (global indices in sidx), C floats each,
-// moved in 16-byte chunks: chunk q = tid + 256 k of the batch's B * C / 4.
-// load_features issues the global loads into registers; store_features
-// writes them to LDS once the blend of the current batch is done, so the
-// loads overlap that blend and the blend's LDS reads never wait for them.
-template <int C, int B>
-struct FeatChunks {
-  static constexpr int N = (B * C / 4 + 255) / 256;   // chunks per lane (at most)
-  f4v v[N];                                           // native vectors: kept in VGPRs
-};
-
-template <int C, int B>
-__device__ __forceinline__ void load_features(const float* __restrict__ feat, int64_t g_off,
-                                              const int32_t* sidx, int nb, FeatChunks<C, B>& fc) {
-  constexpr int CHUNKS = C / 4;
-#pragma unroll
-  for (int k = 0; k < FeatChunks<C, B>::N; ++k) {
-    const int q = (int)threadIdx.x + 256 * k;
-    const int r = q / CHUNKS, p = q % CHUNKS;
-    if (r < nb) {
-      const int64_t g = (int64_t)sidx[r] - g_off;
-      // global address space: a generic (flat) load would also count against
-      // the LDS counter and make the blend's LDS waits wait for it
-      fc.v[k] = *(const __attribute__((address_space(1))) f4v*)(feat + g * C + 4 * p);
-    }
-  }
-}
-
-template <int C, int B>
-__device__ __forceinline__ void store_features(float* dst, int nb, const FeatChunks<C, B>& fc) {
-  constexpr int CHUNKS = C / 4;
-#pragma unroll
-  for (int k = 0; k < FeatChunks<C, B>::N; ++k) {
-    const int q = (int)threadIdx.x + 256 * k;
-    if (q / CHUNKS < nb) reinterpret_cast<f4v*>(dst)[q] = fc.v[k];
-  }
-}
-
 // this lane's C/4 contiguous features of a row (LDS), for the MFMA B operands
 template <int NM>
 __device__ __forceinline__ void load_slice(const float* p, float (&fl)[NM]) {
@@ -105,18 +75,56 @@ struct WorkCount {
   uint32_t n_eval = 0, n_blend = 0, steps = 0, steps_pass = 0, steps_blend = 0;
 };
 
+typedef __attribute__((address_space(3))) void lds_void;
+
+// LDS of one staged batch (one of two, each a separate __shared__ object so
+// that the compiler can tell the DMA into one from the walk over the other)
 template <int C, int B>
-struct RenderShared {
-  float4 st[2][B];
-  float4 cq[2][B];
-  int32_t sidx[2][B];
-  __align__(16) float fe[2][B * C];
+struct BatchLDS {
+  float4 st[B];                     // 2D state (make_state)
+  float4 cq[B];
+  double2 xy[B];                    // raw projected state, DMA target
+  float4 co[B];
+  int32_t ix[B];                    // Gaussian indices
+  __align__(16) float fe[B * C];    // feature rows, DMA target
 };
+
+// Issue the DMA of batch entries [0, nb) (indices in L.ix): feature rows
+// as 16-byte chunks spread over the four waves, raw xy by wave 0 and raw
+// conic by wave 1 (one 16-byte load per lane each).
+template <int C, int B>
+__device__ __forceinline__ void dma_batch(const BatchArgs& a, const float* __restrict__ feat, int64_t g_off,
+                                          BatchLDS<C, B>& L, int nb, int w, int lane) {
+  constexpr int CHUNKS = C / 4;
+  constexpr int INSTR = B * CHUNKS / 64;     // wave-wide feature loads per batch
+  constexpr int PER = (INSTR + 3) / 4;       // ... per wave
+  // all index reads first: an LDS read after a DMA into the same object
+  // would have to wait for the DMA
+  const int g0 = L.ix[lane < nb ? lane : 0];
+  int gi[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int q = (w + 4 * i) * 64 + lane;
+    const int r = q / CHUNKS;
+    gi[i] = L.ix[r < nb ? r : 0];
+  }
+  if (w == 0) __builtin_amdgcn_global_load_lds((const void*)(a.xy + g0), (lds_void*)L.xy, 16, 0, 0);
+  if (w == 1) __builtin_amdgcn_global_load_lds((const void*)(a.conic_o + g0), (lds_void*)L.co, 16, 0, 0);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int k = w + 4 * i;
+    if (k < INSTR) {
+      const int p = ((k * 64 + lane) % CHUNKS);
+      __builtin_amdgcn_global_load_lds((const void*)(feat + (int64_t)(gi[i] - g_off) * C + 4 * p),
+                                       (lds_void*)(L.fe + k * 256), 16, 0, 0);
+    }
+  }
+}
 
 // Blend one tile (tile-local coordinates tx, ty of request q).
 template <int C, int B, bool COUNT>
 __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q, int gtile, int tx,
-                                            int ty, RenderShared<C, B>& sh, WorkCount& wc) {
+                                            int ty, BatchLDS<C, B>& L0, BatchLDS<C, B>& L1, WorkCount& wc) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int W = q.cam.W, H = q.cam.H;
   const int lx = ((w & 1) << 3) | (lane & 7);
@@ -138,66 +146,42 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   for (int m = 0; m < NM; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
   float T = 1.f;
   int last = -1;
-  // +inf once the pixel has ended (or lies outside the image): added to the
-  // exponent before the threshold test, it fails every later test
   float dead = inside ? 0.f : INFINITY;
   int stop_pos = -1;                  // list position that ended the pixel (COUNT only)
 
   const int nbatch = (len + B - 1) / B;
-  // prologue: indices of batches 0 and 1, then batch 0 staged
+  // prologue: indices of batches 0 and 1, batch 0 fetched and staged
   if (tid < B) {
-    sh.sidx[0][tid] = tid < len ? a.sorted[s + tid] : 0;
-    sh.sidx[1][tid] = B + tid < len ? a.sorted[s + B + tid] : 0;
+    L0.ix[tid] = tid < len ? a.sorted[s + tid] : 0;
+    L1.ix[tid] = B + tid < len ? a.sorted[s + B + tid] : 0;
   }
   __syncthreads();
   if (nbatch > 0) {
-    FeatChunks<C, B> fc;
-    load_features<C, B>(feat, g_off, sh.sidx[0], min(B, len), fc);
-    if (tid < B && tid < len) {
-      const int g = sh.sidx[0][tid];
-      float4 s0, s1;
-      make_state(a.xy[g], a.conic_o[g], ox, oy, s0, s1);
-      sh.st[0][tid] = s0;
-      sh.cq[0][tid] = s1;
-    }
-    store_features<C, B>(sh.fe[0], min(B, len), fc);
+    dma_batch<C, B>(a, feat, g_off, L0, min(B, len), w, lane);
+    __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
+  if (tid < B && tid < len) make_state(L0.xy[tid], L0.co[tid], ox, oy, L0.st[tid], L0.cq[tid]);
+  __syncthreads();
 
-  for (int b = 0; b < nbatch; ++b) {
-    const int cur = b & 1, nxt = cur ^ 1;
+  auto step = [&](BatchLDS<C, B>& cur, BatchLDS<C, B>& nxt, int b) -> bool {
     const int b0 = b * B;
     const int nb = min(B, len - b0);
-    // ---- prefetch batch b+1 (features, state and next indices into registers)
     const bool more = b + 1 < nbatch;
     const int nb1 = more ? min(B, len - b0 - B) : 0;
-    double2 pxy = make_double2(0.0, 0.0);
-    float4 pco = make_float4(0.f, 0.f, 0.f, 0.f);
+    // ---- batch b+1 on its way into LDS; indices of batch b+2 into a register
+    if (more) dma_batch<C, B>(a, feat, g_off, nxt, nb1, w, lane);
     int pidx = 0;
-    FeatChunks<C, B> fc;
-    if (more) {
-      load_features<C, B>(feat, g_off, sh.sidx[nxt], nb1, fc);
-      if (tid < nb1) {
-        const int g = sh.sidx[nxt][tid];
-        pxy = a.xy[g];
-        pco = a.conic_o[g];
-      }
-      if (tid < B && b0 + 2 * B + tid < len) pidx = a.sorted[s + b0 + 2 * B + tid];
-    }
+    if (more && tid < B && b0 + 2 * B + tid < len) pidx = a.sorted[s + b0 + 2 * B + tid];
     // ---- blend batch b: walk the Gaussians that reach this wave's quadrant
-    const float4* stc = sh.st[cur];
-    const float4* cqc = sh.cq[cur];
-    const float* fec = sh.fe[cur];
-    for (int m0 = 0; m0 < nb; m0 += 64) {
-      const int jj = m0 + lane;
-      const bool reach = jj < nb && (__float_as_uint(cqc[jj].w) & qbit) != 0;
+    {
+      const bool reach = lane < nb && (__float_as_uint(cur.cq[lane].w) & qbit) != 0;
       uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
-      if (!mask) continue;
       while (mask) {
-        const int j = m0 + (int)__builtin_ctzll(mask);
+        const int j = (int)__builtin_ctzll(mask);
         mask &= mask - 1;
         if (__builtin_amdgcn_ballot_w64(dead == 0.f) == 0) break;
-        const float4 gs = stc[j], qv = cqc[j];
+        const float4 gs = cur.st[j], qv = cur.cq[j];
         const float P = exponent(gs, qv, fpx, fpy);
         const float Pm = P + dead;
         if (COUNT) ++wc.steps;
@@ -218,25 +202,27 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
           if (__builtin_amdgcn_ballot_w64(wgt > 0.f) != 0) {
             if (COUNT) ++wc.steps_blend;
             float fl[NM];
-            load_slice<NM>(fec + j * C + NM * q4, fl);
+            load_slice<NM>(cur.fe + j * C + NM * q4, fl);
 #pragma unroll
             for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt, fl[m], acc[m], 0, 0, 0);
           }
         }
       }
     }
-    // ---- finish staging batch b+1
+    // ---- finish batch b+1: every wave's DMA complete, then its 2D state
+    __builtin_amdgcn_s_waitcnt(0);
+    const int alive = __syncthreads_count(dead == 0.f);
     if (more) {
-      if (tid < nb1) {
-        float4 s0, s1;
-        make_state(pxy, pco, ox, oy, s0, s1);
-        sh.st[nxt][tid] = s0;
-        sh.cq[nxt][tid] = s1;
-      }
-      store_features<C, B>(sh.fe[nxt], nb1, fc);
-      if (tid < B) sh.sidx[cur][tid] = pidx;
+      if (tid < nb1) make_state(nxt.xy[tid], nxt.co[tid], ox, oy, nxt.st[tid], nxt.cq[tid]);
+      if (tid < B) cur.ix[tid] = pidx;
     }
-    if (__syncthreads_count(dead == 0.f) == 0) break;
+    __syncthreads();
+    return alive != 0;
+  };
+  for (int b = 0; b < nbatch; b += 2) {
+    if (!step(L0, L1, b)) break;
+    if (b + 1 >= nbatch) break;
+    if (!step(L1, L0, b + 1)) break;
   }
   if (q.bg) {                         // F += T_final bg, as one more rank-1 update
     float bl[NM];
@@ -285,11 +271,12 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
 // serving batch) rather than inline (a single render); the two are separate
 // instantiations so that each keeps its own launch statistics.
 template <int C, int B, bool COUNT, bool TABLE>
-__global__ void __launch_bounds__(256) k_render(BatchArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_render(BatchArgs a) {
   if (a.dev->overflow) return;
   if (!TABLE) a.table = nullptr;
   const BatchHdr h = batch_hdr(a);
-  __shared__ RenderShared<C, B> sh;
+  __shared__ BatchLDS<C, B> L0;
+  __shared__ BatchLDS<C, B> L1;
   __shared__ int s_tile;
   const int tid = threadIdx.x;
   WorkCount wc;
@@ -306,7 +293,7 @@ __global__ void __launch_bounds__(256) k_render(BatchArgs a) {
     if (r < 0) break;
     const ReqDev& q = batch_req(a, r);
     const int lt = t - q.tile_off;
-    render_tile<C, B, COUNT>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, sh, wc);
+    render_tile<C, B, COUNT>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, L0, L1, wc);
   }
   if (COUNT) {
     __shared__ unsigned long long cnt[5];
