@@ -43,34 +43,6 @@ __device__ __forceinline__ void make_state(double2 xy, float4 co, double ox, dou
   cq = make_float4(-0.5f * LOG2E * co.x, -LOG2E * co.y, -0.5f * LOG2E * co.z, __uint_as_float(mask));
 }
 
-// Whether the alpha >= 1/255 ellipse of a Gaussian can reach the 8x8
-// quadrant qd of the tile at (ox, oy): the same box as make_state's mask
-// bit, evaluated for one quadrant with the hardware's approximate log2,
-// reciprocal and square root (the box is widened by CULL_MARGIN, far more
-// than their error, so the test stays conservative).
-__device__ __forceinline__ bool reaches_quadrant(double2 xy, float4 co, double ox, double oy, int qd) {
-  const float o = co.w;
-  if (!(o * 255.f >= 1.f)) return false;
-  const float u = (float)(xy.x - ox), v = (float)(xy.y - oy);
-  const float rho = (2.f * 0.69314718f) * __builtin_amdgcn_logf(255.f * o);
-  const float rdet = __builtin_amdgcn_rcpf(co.x * co.z - co.y * co.y);
-  const float ex = __builtin_amdgcn_sqrtf(fmaxf(rho * co.z * rdet, 0.f)) + CULL_MARGIN;
-  const float ey = __builtin_amdgcn_sqrtf(fmaxf(rho * co.x * rdet, 0.f)) + CULL_MARGIN;
-  const float x0 = (float)((qd & 1) * 8) + 0.5f, y0 = (float)((qd >> 1) * 8) + 0.5f;
-  return (u + ex >= x0) & (u - ex <= x0 + 7.f) & (v + ey >= y0) & (v - ey <= y0 + 7.f);
-}
-
-// make_state without the quadrant mask (cq.w = 0), for a Gaussian already
-// known to reach the quadrant being walked
-__device__ __forceinline__ void make_state_nomask(double2 xy, float4 co, double ox, double oy,
-                                                  float4& st, float4& cq) {
-  const float u = (float)(xy.x - ox), v = (float)(xy.y - oy);
-  const float o = co.w;
-  const float thr = o * 255.f >= 1.f ? -log2f(255.f * o) : INFINITY;
-  st = make_float4(u, v, o, thr);
-  cq = make_float4(-0.5f * LOG2E * co.x, -LOG2E * co.y, -0.5f * LOG2E * co.z, 0.f);
-}
-
 // log2 of the Gaussian at tile-local pixel centre (fpx, fpy):
 // -(A dx^2 + C dy^2)/2 - B dx dy in units of log2(e)
 __device__ __forceinline__ float exponent(float4 st, float4 cq, float fpx, float fpy) {
