@@ -55,7 +55,7 @@ def copy_calibration():
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_render_hbm_traffic_realistic_frame.md")
 RENDER_SOURCES = [os.path.join(ROOT, "paper_2405_14866_amd", "csrc", f)
-                  for f in ("render_fwd.hip", "tg_internal.h")]
+                  for f in ("render_fwd.hip", "blend_common.h", "tg_internal.h")]
 
 
 def render_source_digest():
