@@ -18,10 +18,12 @@
 //            atomics hand out slots inside it; each slot receives the 64-bit
 //            key (depth << 32) | index.  The order inside a segment is not
 //            deterministic here; the sort makes it so;
-//   k_sort   one 256-lane workgroup per tile: the segment is loaded into LDS
-//            and sorted by a stable least-significant-digit radix sort with
-//            8-bit digits (ranking within each wave64 by ballot matching,
-//            digit offsets by a wave-level scan, four barriers per pass) on
+//   k_sort   one 256-lane workgroup per tile, tiles taken longest first
+//            (the scan's order): the segment is loaded (eight keys per lane
+//            in flight at once) into LDS and sorted by a stable
+//            least-significant-digit radix sort with 8-bit digits (digit
+//            counts by LDS atomics, ranking within each wave64 by ballot
+//            matching, digit offsets by a wave-level scan) on
 //            the depth bits alone, re-based to the segment's minimum (about
 //            three passes); runs of equal depth (frequent: a tile spans a
 //            narrow depth range) are then ordered by index, one lane per
@@ -29,8 +31,9 @@
 //            the composite (depth - min, index - min) key.
 //            Either way the result is the unique (depth, index) order.
 //            Segments up to 2048 keys run in a 32 KB-LDS launch (four
-//            workgroups per CU), larger ones in a second launch with 128 KB,
-//            and beyond 8192 keys on global scratch buffers.
+//            workgroups per CU), larger ones in a second launch with 128 KB
+//            whose small grid walks the head of the tile order, and beyond
+//            8192 keys on global scratch buffers.
 //
 // Compared with a global LSD sort of all K keys (4-6 passes of K x 12-24 B
 // over HBM plus a launch per pass), the keys cross HBM about three times.
@@ -257,13 +260,7 @@ __device__ __forceinline__ void radix_pass(Ptr src, Ptr dst, int n, int shift, S
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int per = ((n + 255) / 256) * 64;
   const int b = min(n, w * per), e = min(n, b + per);
-  for (int j0 = b; j0 < e; j0 += 64) {
-    const int j = j0 + lane;
-    const bool valid = j < e;
-    const uint32_t d = valid ? (uint32_t)(src[j] >> shift) & 255u : 0u;
-    const uint64_t peers = match_digit(d, valid);
-    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&sh.hist[w][d], (uint32_t)__popcll(peers));
-  }
+  for (int j = b + lane; j < e; j += 64) atomicAdd(&sh.hist[w][(uint32_t)(src[j] >> shift) & 255u], 1u);
   __syncthreads();
   // digit-major, wave-minor exclusive offsets; wave w scans digits [64 w, 64 w + 64)
   const int d = 64 * w + lane;
@@ -315,29 +312,34 @@ constexpr int MAX_TIE_RUN = 32;
 // result is the (depth, index) order.  Segments above CAP run the
 // composite sort on the global scratch buffers.
 template <int CAP>
-__global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
-  if (a.dev->overflow) return;
-  const int t = blockIdx.x;
-  if (t >= batch_hdr(a).n_tiles) return;
-  const int s = a.tile_start[t], e = a.tile_start[t + 1];
-  const int n = e - s;
-  if (n <= lo || n > hi) return;
+__device__ __forceinline__ void sort_tile(const BatchArgs& a, int s, int n, uint64_t* bufA, uint64_t* bufB,
+                                          SortShared& sh) {
   const int tid = threadIdx.x, w = tid >> 6;
   if (n == 1) {
     if (tid == 0) a.sorted[s] = (int32_t)(uint32_t)a.keys[s];
     return;
   }
-  __shared__ uint64_t bufA[CAP];
-  __shared__ uint64_t bufB[CAP];
-  __shared__ SortShared sh;
   for (int q = tid; q < 4 * 256; q += 256) (&sh.hist[0][0])[q] = 0;
-  // ranges of depth and index in the segment
+  // ranges of depth and index in the segment; the keys are loaded eight per
+  // lane with all loads in flight at once (a segment up to 2048 keys stays
+  // in registers until it is re-based into LDS)
+  constexpr int PER = 8;
+  uint64_t kv[PER];
   uint64_t dmin = ~0ull, dmax = 0, imin = ~0ull, imax = 0;
-  for (int j = tid; j < n; j += 256) {
-    const uint64_t k = a.keys[s + j];
-    const uint64_t d = k >> 32, i = k & 0xffffffffull;
-    dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
-    imin = i < imin ? i : imin; imax = i > imax ? i : imax;
+  for (int j0 = 0; j0 < n; j0 += 256 * PER) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int j = j0 + tid + 256 * i;
+      kv[i] = j < n ? a.keys[s + j] : 0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (j0 + tid + 256 * i < n) {
+        const uint64_t d = kv[i] >> 32, ix = kv[i] & 0xffffffffull;
+        dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
+        imin = ix < imin ? ix : imin; imax = ix > imax ? ix : imax;
+      }
+    }
   }
   dmin = wave_min_u64(dmin); dmax = wave_max_u64(dmax);
   imin = wave_min_u64(imin); imax = wave_max_u64(imax);
@@ -351,9 +353,17 @@ __global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
   const uint64_t imask = ib == 0 ? 0ull : (~0ull >> (64 - ib));
   if (n <= CAP) {
     // depth-only pass set: element = (depth - dmin) << 32 | index
-    for (int j = tid; j < n; j += 256) {
-      const uint64_t k = a.keys[s + j];
-      bufA[j] = (((k >> 32) - dmin) << 32) | (k & 0xffffffffull);
+    if (n <= 256 * PER) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int j = tid + 256 * i;
+        if (j < n) bufA[j] = (((kv[i] >> 32) - dmin) << 32) | (kv[i] & 0xffffffffull);
+      }
+    } else {
+      for (int j = tid; j < n; j += 256) {
+        const uint64_t k = a.keys[s + j];
+        bufA[j] = (((k >> 32) - dmin) << 32) | (k & 0xffffffffull);
+      }
     }
     __syncthreads();
     uint64_t* res = radix_sort<uint64_t*>(bufA, bufB, n, 32, db, sh);
@@ -396,6 +406,30 @@ __global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
   }
 }
 
+// Tiles are taken in the scan's order (descending key count), so the
+// longest segments start first.  With LOOP, a small grid walks the head
+// of that order and stops at the first tile too short for it.
+template <int CAP, bool LOOP>
+__global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
+  if (a.dev->overflow) return;
+  __shared__ uint64_t bufA[CAP];
+  __shared__ uint64_t bufB[CAP];
+  __shared__ SortShared sh;
+  const int nt = batch_hdr(a).n_tiles;
+  for (int i = blockIdx.x; i < nt; i += gridDim.x) {
+    const int t = a.tile_order[i];
+    const int s = a.tile_start[t];
+    const int n = a.tile_start[t + 1] - s;
+    if (n <= lo) {
+      if (LOOP && n < ((ORDER_BUCKETS - 1) << ORDER_SHIFT)) break;   // the rest are shorter still
+      continue;
+    }
+    if (n > hi) continue;
+    sort_tile<CAP>(a, s, n, bufA, bufB, sh);
+    __syncthreads();                 // LDS is reused by the next tile
+  }
+}
+
 constexpr int SORT_SMALL = 2048;   // segments up to this size: 32 KB of LDS keys, 4 workgroups per CU
 constexpr int SORT_LARGE = 8192;   // larger segments: 128 KB of LDS keys, beyond it global scratch
 
@@ -414,9 +448,10 @@ hipError_t launch_bin_sort(const BatchArgs& a, int64_t grid_gauss, int32_t grid_
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(k_fill, dim3(grid), dim3(1024), shm, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(k_sort<SORT_SMALL>, dim3(gt), dim3(256), 0, s, a, 0, SORT_SMALL);
+  hipLaunchKernelGGL((k_sort<SORT_SMALL, false>), dim3(gt), dim3(256), 0, s, a, 0, SORT_SMALL);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(k_sort<SORT_LARGE>, dim3(gt), dim3(256), 0, s, a, SORT_SMALL, 0x7fffffff);
+  hipLaunchKernelGGL((k_sort<SORT_LARGE, true>), dim3(gt < 256 ? gt : 256), dim3(256), 0, s, a, SORT_SMALL,
+                     0x7fffffff);
   return hipGetLastError();
 }
 

@@ -29,11 +29,14 @@
 //     Gaussians that reach its quadrant, in list order (s_ff1 over the
 //     ballot mask), so Gaussians that only touch the other quadrants cost
 //     it nothing;
-//   * the per-Gaussian body has a single wave-uniform branch for the
-//     exponential and one for the feature accumulation; the rest are
-//     selects.  Each branch condition is one vector compare (the threshold
-//     test thr <= P <= 0 is a median, and an ended pixel carries +inf that
-//     is added to its exponent), so the ballot needs no mask conversion;
+//   * the per-Gaussian body has a single wave-uniform branch, around the
+//     feature accumulation; the exponent, alpha and the transmittance
+//     update are computed for every walked Gaussian and committed with
+//     selects (a branch around them saved less than its pipeline bubbles
+//     cost).  The threshold test thr <= P <= 0 is a median, an ended pixel
+//     carries +inf that is added to its exponent, and the accumulation's
+//     condition is one vector compare, so the ballot needs no mask
+//     conversion;
 //   * the feature accumulation of a step is the rank-1 update F += w f^T of
 //     the wave's 64 pixels x C channels (w: each lane's blend weight, 0 where
 //     it does not blend).  It runs on the matrix cores as C/4
@@ -177,35 +180,64 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     {
       const bool reach = lane < nb && (__float_as_uint(cur.cq[lane].w) & qbit) != 0;
       uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
+      // two reaching Gaussians per iteration: their exponents and alphas
+      // are independent and overlap; the transmittance updates and the
+      // feature accumulations then run in list order
       while (mask) {
-        const int j = (int)__builtin_ctzll(mask);
+        const int j1 = (int)__builtin_ctzll(mask);
         mask &= mask - 1;
-        if (__builtin_amdgcn_ballot_w64(dead == 0.f) == 0) break;
-        const float4 gs = cur.st[j], qv = cur.cq[j];
-        const float P = exponent(gs, qv, fpx, fpy);
-        const float Pm = P + dead;
-        if (COUNT) ++wc.steps;
-        if (__builtin_amdgcn_ballot_w64(passes(Pm, gs.w)) != 0) {
-          const bool pass = passes(Pm, gs.w);
-          if (COUNT) ++wc.steps_pass;
-          const float al = blend_alpha(gs.z, P);
-          const bool ok = pass & (al >= 1.f / 255.f);
-          const float Tn = T * (1.f - al);
+        const bool has2 = mask != 0;
+        const int j2 = has2 ? (int)__builtin_ctzll(mask) : j1;
+        if (has2) mask &= mask - 1;
+        const float4 gs1 = cur.st[j1], qv1 = cur.cq[j1];
+        const float4 gs2 = cur.st[j2], qv2 = cur.cq[j2];
+        const float P1 = exponent(gs1, qv1, fpx, fpy);
+        const float P2 = exponent(gs2, qv2, fpx, fpy);
+        const float al1 = blend_alpha(gs1.z, P1);
+        const float al2 = blend_alpha(gs2.z, P2);
+        if (COUNT) wc.steps += has2 ? 2 : 1;
+        float wgt1, wgt2;
+        {
+          const bool pass = passes(P1 + dead, gs1.w);
+          if (COUNT && __builtin_amdgcn_ballot_w64(pass) != 0) ++wc.steps_pass;
+          const bool ok = pass & (al1 >= 1.f / 255.f);
+          const float Tn = T * (1.f - al1);
           const bool stop = ok & (Tn < 1e-4f);
           const bool blend = ok & !stop;
-          if (COUNT && stop) stop_pos = b0 + j;
+          if (COUNT && stop) stop_pos = b0 + j1;
           dead = stop ? INFINITY : dead;
-          const float wgt = blend ? al * T : 0.f;
+          wgt1 = blend ? al1 * T : 0.f;
           T = blend ? Tn : T;
-          last = blend ? b0 + j : last;
+          last = blend ? b0 + j1 : last;
           if (COUNT && blend) ++wc.n_blend;
-          if (__builtin_amdgcn_ballot_w64(wgt > 0.f) != 0) {
-            if (COUNT) ++wc.steps_blend;
-            float fl[NM];
-            load_slice<NM>(cur.fe + j * C + NM * q4, fl);
+        }
+        {
+          const bool pass = has2 & passes(P2 + dead, gs2.w);
+          if (COUNT && __builtin_amdgcn_ballot_w64(pass) != 0) ++wc.steps_pass;
+          const bool ok = pass & (al2 >= 1.f / 255.f);
+          const float Tn = T * (1.f - al2);
+          const bool stop = ok & (Tn < 1e-4f);
+          const bool blend = ok & !stop;
+          if (COUNT && stop) stop_pos = b0 + j2;
+          dead = stop ? INFINITY : dead;
+          wgt2 = blend ? al2 * T : 0.f;
+          T = blend ? Tn : T;
+          last = blend ? b0 + j2 : last;
+          if (COUNT && blend) ++wc.n_blend;
+        }
+        if (__builtin_amdgcn_ballot_w64(wgt1 > 0.f) != 0) {
+          if (COUNT) ++wc.steps_blend;
+          float fl[NM];
+          load_slice<NM>(cur.fe + j1 * C + NM * q4, fl);
 #pragma unroll
-            for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt, fl[m], acc[m], 0, 0, 0);
-          }
+          for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt1, fl[m], acc[m], 0, 0, 0);
+        }
+        if (__builtin_amdgcn_ballot_w64(wgt2 > 0.f) != 0) {
+          if (COUNT) ++wc.steps_blend;
+          float fl[NM];
+          load_slice<NM>(cur.fe + j2 * C + NM * q4, fl);
+#pragma unroll
+          for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt2, fl[m], acc[m], 0, 0, 0);
         }
       }
     }
