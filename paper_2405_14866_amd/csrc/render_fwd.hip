@@ -29,11 +29,13 @@
 //     Gaussians that reach its quadrant, in list order (s_ff1 over the
 //     ballot mask), so Gaussians that only touch the other quadrants cost
 //     it nothing;
-//   * the per-Gaussian body has a single wave-uniform branch, around the
-//     feature accumulation; the exponent, alpha and the transmittance
-//     update are computed for every walked Gaussian and committed with
-//     selects (a branch around them saved less than its pipeline bubbles
-//     cost).  The threshold test thr <= P <= 0 is a median, an ended pixel
+//   * the walk takes two reaching Gaussians per iteration: their exponents
+//     and alphas are independent and overlap, then their transmittance
+//     updates and feature accumulations run in list order.  The only
+//     wave-uniform branches are around the feature accumulations; the
+//     exponent, alpha and the transmittance update are computed for every
+//     walked Gaussian and committed with selects (a branch around them
+//     saved less than its pipeline bubbles cost).  The threshold test thr <= P <= 0 is a median, an ended pixel
 //     carries +inf that is added to its exponent, and the accumulation's
 //     condition is one vector compare, so the ballot needs no mask
 //     conversion;
