@@ -14,10 +14,19 @@
 //    sqrt are correctly rounded on gfx950), so culling, rectangles and keys
 //    are reproducible bit for bit by any IEEE implementation of the same
 //    sequence;
-//  * the continuous 2D state (u, v, conic) in FP64: the render later forms
-//    pixel offsets d = p - (u, v) relative to its tile, which keeps them
-//    accurate to ~1e-7 px at any image size.  The kernel is HBM-bound, so
-//    the FP64 arithmetic (full rate on CDNA4's vector FP64 units) is free.
+//  * the continuous 2D state in FP64: the mean (u, v), the conic, and the
+//    tile-independent factors of the blend's exponent.  With Sigma' the
+//    dilated 2D covariance (entries a, b, c) the quadratic form completes to
+//      d^T Sigma'^-1 d = (c / det) (dx - (b / c) dy)^2 + dy^2 / c,
+//    so that, in units of log2(e), the exponent is -(z1^2 + z2^2) with
+//    z1 = s (dx + k dy), z2 = r dy, s = sqrt(log2(e) c / (2 det)),
+//    k = -b / c, r = sqrt(log2(e) / (2 c)); the factors come straight from
+//    Sigma' (no cancellation in det(Sigma'^-1) for elongated Gaussians).
+//    The alpha >= 1/255 ellipse d^T Sigma'^-1 d <= 2 ln(255 o) has the
+//    half-extents sqrt(2 ln(255 o) a) and sqrt(2 ln(255 o) c).  The render
+//    forms pixel offsets relative to its tile from the FP64 mean, which keeps
+//    them accurate to ~1e-7 px at any image size.  The kernel is HBM-bound,
+//    so the FP64 arithmetic (full rate on CDNA4's vector FP64 units) is free.
 #include "tg_internal.h"
 
 namespace tg {
@@ -117,6 +126,8 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
   uint2 rect = make_uint2(1u, 0u);   // empty
   double2 xy = make_double2(0.0, 0.0);
   float4 co = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 wq = make_float4(0.f, 0.f, 0.f, -INFINITY);
+  float4 ext = make_float4(-INFINITY, -INFINITY, op, 0.f);
   if (rc.ok) {
     // continuous state in FP64
     const double X = mx, Y = my, Z = mz;
@@ -152,11 +163,21 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
     const double det = sa * sc - sb * sb;
     if (det > 0.0) {
       co = make_float4((float)(sc / det), (float)(-sb / det), (float)(sa / det), op);
+      constexpr double L2E = 1.4426950408889634;
+      const double sw = sqrt(0.5 * L2E * sc / det);
+      wq = make_float4((float)sw, (float)(sw * (-sb / sc)), (float)sqrt(0.5 * L2E / sc), (float)log2((double)op));
+      if ((double)op * 255.0 >= 1.0) {
+        const double rho = 2.0 * log(255.0 * (double)op);
+        ext.x = (float)sqrt(rho * sa);
+        ext.y = (float)sqrt(rho * sc);
+      }
       rect = make_uint2((uint32_t)rc.x0 | ((uint32_t)rc.x1 << 16), (uint32_t)rc.y0 | ((uint32_t)rc.y1 << 16));
     }
   }
   a.xy[gi] = xy;
   a.conic_o[gi] = co;
+  a.wq[gi] = wq;
+  a.ext[gi] = ext;
   a.rect[gi] = rect;
   a.depth[gi] = rc.ok ? rc.key : 0xffffffffu;
 }

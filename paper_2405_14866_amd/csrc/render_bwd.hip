@@ -41,9 +41,10 @@ constexpr int GROUP = 16;      // Gaussians per matrix-core reduction
 
 template <int C>
 struct BwdShared {
-  float4 st[BWD_B];            // as in the forward
-  float4 cq[BWD_B];
+  float4 wq[BWD_B];            // exponent factors, as in the forward
+  float4 st[BWD_B];            // (c1, c2, u, v): tile offsets and tile-relative mean
   float4 cn[BWD_B];            // unscaled conic A, B, C and opacity
+  uint32_t qm[BWD_B];          // quadrant masks
   int32_t sidx[BWD_B];
   __align__(16) float fe[BWD_B * C];
   int32_t wl[4][BWD_B];        // per wave: reaching batch entries, last first
@@ -147,12 +148,12 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
     __syncthreads();                          // the previous batch is done with the buffers
     if (tid < nb) {
       const int gi = a.sorted[s + b0 + tid];
-      const float4 co = a.conic_o[gi];
-      float4 s0, s1;
-      make_state(a.xy[gi], co, ox, oy, s0, s1);
-      sh.st[tid] = s0;
-      sh.cq[tid] = s1;
-      sh.cn[tid] = co;
+      const float4 wq = a.wq[gi];
+      const TileState ts = make_state(a.xy[gi], wq, a.ext[gi], ox, oy);
+      sh.wq[tid] = wq;
+      sh.st[tid] = make_float4(ts.c1, ts.c2, ts.u, ts.v);
+      sh.qm[tid] = ts.mask;
+      sh.cn[tid] = a.conic_o[gi];
       sh.sidx[tid] = gi;
     }
     for (int k = tid; k < nb * (C / 4); k += 256) {
@@ -164,7 +165,7 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
     __syncthreads();
     if (b0 > wmax) continue;                  // no pixel of this quadrant reaches this batch
     // reaching entries of the batch, last first
-    const bool reach = lane < nb && (__float_as_uint(sh.cq[lane].w) & qbit) != 0 && b0 + lane <= wmax;
+    const bool reach = lane < nb && (sh.qm[lane] & qbit) != 0 && b0 + lane <= wmax;
     const uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
     const int cnt = __builtin_popcountll(mask);
     if (reach) sh.wl[w][__builtin_popcountll(lane == 63 ? 0ull : mask >> (lane + 1))] = lane;
@@ -175,14 +176,12 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
       for (int i = 0; i < n; ++i) {
         const int j = sh.wl[w][g0 + i];
         const int pos = b0 + j;
-        const float4 gs = sh.st[j], qv = sh.cq[j];
-        const float P = exponent(gs, qv, fpx, fpy);
-        const bool ok = pos <= last && passes(P, gs.w);
+        const float4 wq = sh.wq[j], st = sh.st[j];
+        const float oG = __builtin_amdgcn_exp2f(exponent(wq, st.x, st.y, fpx, fpy));
+        const float al = fminf(0.99f, oG);
+        const bool contrib = pos <= last && al >= ALPHA_MIN;
         float wv = 0.f, dv = 0.f;
-        if (__builtin_amdgcn_ballot_w64(ok) != 0) {
-          const float G = __builtin_amdgcn_exp2f(P);
-          const float al = fminf(0.99f, gs.z * G);
-          const bool contrib = ok & (al >= 1.f / 255.f);
+        {
           if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
             cmask |= 1u << i;
             const float* fr = sh.fe + j * C;
@@ -197,7 +196,7 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
             const float dLda = Ti * fg + (gAT - sgS) * __builtin_amdgcn_rcpf(oma);
             const float wgt = al * Ti;
             wv = contrib ? wgt : 0.f;
-            dv = contrib && gs.z * G <= 0.99f ? dLda * al : 0.f;
+            dv = contrib && oG <= 0.99f ? dLda * al : 0.f;
             sgS = contrib ? __builtin_fmaf(wgt, fg, sgS) : sgS;
             T = contrib ? Ti : T;
           }
@@ -244,10 +243,10 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
       if (lane < n && ((cmask >> lane) & 1u)) {
         const int j = sh.wl[w][g0 + lane];
         const int gi = sh.sidx[j];
-        const float4 gs = sh.st[j], cn = sh.cn[j];
+        const float4 st = sh.st[j], cn = sh.cn[j];
         const float* m = sh.mom[w][lane];
         // pixel offsets d = p - (u, v) with p and (u, v) relative to the quadrant centre
-        const float u = gs.x - (float)(qx0 + 4), v = gs.y - (float)(qy0 + 4);
+        const float u = st.z - (float)(qx0 + 4), v = st.w - (float)(qy0 + 4);
         const float m1 = m[0], mx = m[1], my = m[2], mxx = m[3], mxy = m[4], myy = m[5];
         const float sdx = mx - u * m1, sdy = my - v * m1;
         const float sdxx = mxx - 2.f * u * mx + u * u * m1;
@@ -260,7 +259,7 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
         atomic_add_global(g2 + 2 * gc, -0.5f * sdxx);
         atomic_add_global(g2 + 3 * gc, -sdxy);
         atomic_add_global(g2 + 4 * gc, -0.5f * sdyy);
-        atomic_add_global(g2 + 5 * gc, m1 / gs.z);
+        atomic_add_global(g2 + 5 * gc, m1 / cn.w);
       }
       __builtin_amdgcn_wave_barrier();
     }

@@ -8,37 +8,37 @@
 // double-buffered in LDS:
 //   * while batch b is blended, batch b+1 is fetched by LDS DMA
 //     (global_load_lds_dwordx4): its feature rows as 16-byte chunks over
-//     the four waves, its raw FP64 2D mean and conic (one 16-byte load per
-//     entry), straight into the other buffer without passing through
-//     VGPRs; the list indices of batch b+2 come into a register.  The two
-//     buffers are separate LDS objects and the batch loop is unrolled by
-//     two, so the compiler can tell the DMA target from the buffer being
-//     walked and the walk never waits for the DMA; each wave waits for its
-//     own DMA before the barrier that ends the batch;
+//     the four waves, its FP64 mean, exponent factors and support extents
+//     (one 16-byte load per entry each), straight into the other buffer
+//     without passing through VGPRs; the list indices of batch b+2 come
+//     into a register.  The two buffers are separate LDS objects and the
+//     batch loop is unrolled by two, so the compiler can tell the DMA target
+//     from the buffer being walked and the walk never waits for the DMA;
+//     each wave waits for its own DMA before the barrier that ends the batch;
 //   * the kernel asks for six waves per SIMD: latency, not issue, bounds the
 //     walk, and the few loop-invariant values that do not fit are kept in
 //     scratch outside the walk;
-//   * per staged Gaussian the state is two float4: (u, v) relative to the
-//     tile origin (converted from the FP64 projection, so pixel offsets are
-//     accurate to ~1e-7 px), opacity, the exponent threshold
-//     log2(1/(255 o)); the conic pre-scaled by -log2(e)/2, and a 4-bit mask
-//     of the quadrants its alpha >= 1/255 ellipse can reach (bounding box
-//     widened by 1/16 px, so no pixel that could pass the threshold is ever
-//     culled and the blend's decisions are those of the plain walk);
+//   * per staged Gaussian the walk reads the projection's exponent factors
+//     (s, s k, r, log2 o) and the tile-dependent offsets (c1, c2), formed in
+//     FP64 from the FP64 mean relative to the tile origin (so pixel offsets
+//     are accurate to ~1e-7 px); log2 of the opacity-weighted Gaussian at a
+//     pixel is then log2 o - z1^2 - z2^2 with z1, z2 affine in the pixel
+//     centre: five FMAs and one v_exp_f32 give o G.  make_state also forms a
+//     4-bit mask of the quadrants its alpha >= 1/255 ellipse can reach
+//     (bounding box widened by 1/16 px, so no pixel that could pass the
+//     threshold is ever culled and the blend's decisions are those of the
+//     plain walk);
 //   * each wave ballots the quadrant bits of the batch and walks only the
 //     Gaussians that reach its quadrant, in list order (s_ff1 over the
 //     ballot mask), so Gaussians that only touch the other quadrants cost
-//     it nothing;
-//   * the walk takes two reaching Gaussians per iteration: their exponents
-//     and alphas are independent and overlap, then their transmittance
-//     updates and feature accumulations run in list order.  The only
-//     wave-uniform branches are around the feature accumulations; the
-//     exponent, alpha and the transmittance update are computed for every
-//     walked Gaussian and committed with selects (a branch around them
-//     saved less than its pipeline bubbles cost).  The threshold test thr <= P <= 0 is a median, an ended pixel
-//     carries +inf that is added to its exponent, and the accumulation's
-//     condition is one vector compare, so the ballot needs no mask
-//     conversion;
+//     it nothing; a wave whose pixels have all ended walks nothing more;
+//   * the walk takes two reaching Gaussians per iteration: their alphas are
+//     independent and overlap, then their decisions and feature
+//     accumulations run in list order.  A pixel's threshold test is one
+//     compare against its own minimum alpha (1/255 while it runs, 2 once it
+//     has ended, so an ended pixel fails every later test); the end of a
+//     pixel and the state updates of a blend sit behind wave-uniform
+//     branches, since a pixel ends once and many steps blend in few pixels;
 //   * the feature accumulation of a step is the rank-1 update F += w f^T of
 //     the wave's 64 pixels x C channels (w: each lane's blend weight, 0 where
 //     it does not blend).  It runs on the matrix cores as C/4
@@ -49,8 +49,7 @@
 //     ds_read_b128 per lane instead of C/4 full-row broadcasts).  This moves
 //     the C FMAs per step off the VALU and cuts the LDS bytes of a step
 //     four-fold; the background enters as one last update with weight T.
-// Per pixel: P = -d^T conic d / 2; skip when P > 0 or when P is below the
-// opacity threshold (alpha < 1/255); alpha = min(0.99, o e^P); a Gaussian
+// Per pixel: alpha = min(0.99, o G); skip when alpha < 1/255; a Gaussian
 // that would take T below 1e-4 ends the pixel without being blended.
 #include "blend_common.h"
 
@@ -86,17 +85,18 @@ typedef __attribute__((address_space(3))) void lds_void;
 // that the compiler can tell the DMA into one from the walk over the other)
 template <int C, int B>
 struct BatchLDS {
-  float4 st[B];                     // 2D state (make_state)
-  float4 cq[B];
-  double2 xy[B];                    // raw projected state, DMA target
-  float4 co[B];
+  float4 wq[B];                     // exponent factors, DMA target (walked as they are)
+  double2 xy[B];                    // FP64 mean, DMA target
+  float4 ext[B];                    // support half-extents, DMA target
+  float4 st[B];                     // (c1, c2, quadrant mask bits, -) from make_state
   int32_t ix[B];                    // Gaussian indices
   __align__(16) float fe[B * C];    // feature rows, DMA target
 };
 
 // Issue the DMA of batch entries [0, nb) (indices in L.ix): feature rows
-// as 16-byte chunks spread over the four waves, raw xy by wave 0 and raw
-// conic by wave 1 (one 16-byte load per lane each).
+// as 16-byte chunks spread over the four waves; the mean by wave 0, the
+// exponent factors by wave 1 and the extents by wave 2 (one 16-byte load
+// per lane each).
 template <int C, int B>
 __device__ __forceinline__ void dma_batch(const BatchArgs& a, const float* __restrict__ feat, int64_t g_off,
                                           BatchLDS<C, B>& L, int nb, int w, int lane) {
@@ -114,7 +114,8 @@ __device__ __forceinline__ void dma_batch(const BatchArgs& a, const float* __res
     gi[i] = L.ix[r < nb ? r : 0];
   }
   if (w == 0) __builtin_amdgcn_global_load_lds((const void*)(a.xy + g0), (lds_void*)L.xy, 16, 0, 0);
-  if (w == 1) __builtin_amdgcn_global_load_lds((const void*)(a.conic_o + g0), (lds_void*)L.co, 16, 0, 0);
+  if (w == 1) __builtin_amdgcn_global_load_lds((const void*)(a.wq + g0), (lds_void*)L.wq, 16, 0, 0);
+  if (w == 2) __builtin_amdgcn_global_load_lds((const void*)(a.ext + g0), (lds_void*)L.ext, 16, 0, 0);
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int k = w + 4 * i;
@@ -124,6 +125,13 @@ __device__ __forceinline__ void dma_batch(const BatchArgs& a, const float* __res
                                        (lds_void*)(L.fe + k * 256), 16, 0, 0);
     }
   }
+}
+
+// tile-dependent state of entry t of a staged batch
+template <int C, int B>
+__device__ __forceinline__ void stage_state(BatchLDS<C, B>& L, int t, double ox, double oy) {
+  const TileState ts = make_state(L.xy[t], L.wq[t], L.ext[t], ox, oy);
+  L.st[t] = make_float4(ts.c1, ts.c2, __uint_as_float(ts.mask), 0.f);
 }
 
 // Blend one tile (tile-local coordinates tx, ty of request q).
@@ -151,7 +159,9 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   for (int m = 0; m < NM; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
   float T = 1.f;
   int last = -1;
-  float dead = inside ? 0.f : INFINITY;
+  // smallest alpha the pixel still takes: 1/255 while it runs, 2 (above any
+  // alpha) once it has ended or when it lies outside the image
+  float amin = inside ? ALPHA_MIN : 2.f;
   int stop_pos = -1;                  // list position that ended the pixel (COUNT only)
 
   const int nbatch = (len + B - 1) / B;
@@ -166,8 +176,35 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
-  if (tid < B && tid < len) make_state(L0.xy[tid], L0.co[tid], ox, oy, L0.st[tid], L0.cq[tid]);
+  if (tid < B && tid < len) stage_state<C, B>(L0, tid, ox, oy);
   __syncthreads();
+
+  // One list entry j (position pos) against this wave's pixels, given its
+  // alpha: the stop / blend decisions, then the state updates and the
+  // feature accumulation, each behind a wave-uniform branch (a pixel ends
+  // at most once, and most steps blend in only some of the pixels).
+  auto visit = [&](const BatchLDS<C, B>& cur, int j, int pos, float al, bool valid) {
+    const bool ok = valid & (al >= amin);
+    const float Tn = __builtin_fmaf(-al, T, T);
+    const bool stop = ok & (Tn < 1e-4f);
+    if (COUNT && __builtin_amdgcn_ballot_w64(ok) != 0) ++wc.steps_pass;
+    if (__builtin_amdgcn_ballot_w64(stop) != 0) {
+      amin = stop ? 2.f : amin;
+      if (COUNT && stop) stop_pos = pos;
+    }
+    const bool blend = ok & !stop;
+    if (__builtin_amdgcn_ballot_w64(blend) != 0) {
+      if (COUNT) ++wc.steps_blend;
+      if (COUNT && blend) ++wc.n_blend;
+      const float wgt = blend ? al * T : 0.f;
+      T = blend ? Tn : T;
+      last = blend ? pos : last;
+      float fl[NM];
+      load_slice<NM>(cur.fe + j * C + NM * q4, fl);
+#pragma unroll
+      for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt, fl[m], acc[m], 0, 0, 0);
+    }
+  };
 
   auto step = [&](BatchLDS<C, B>& cur, BatchLDS<C, B>& nxt, int b) -> bool {
     const int b0 = b * B;
@@ -179,75 +216,34 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     int pidx = 0;
     if (more && tid < B && b0 + 2 * B + tid < len) pidx = a.sorted[s + b0 + 2 * B + tid];
     // ---- blend batch b: walk the Gaussians that reach this wave's quadrant
+    // (none once every pixel of the wave has ended)
     {
-      const bool reach = lane < nb && (__float_as_uint(cur.cq[lane].w) & qbit) != 0;
+      const bool live = __builtin_amdgcn_ballot_w64(amin < 1.f) != 0;
+      const bool reach = live && lane < nb && (__float_as_uint(cur.st[lane].z) & qbit) != 0;
       uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
-      // two reaching Gaussians per iteration: their exponents and alphas
-      // are independent and overlap; the transmittance updates and the
-      // feature accumulations then run in list order
+      // two reaching Gaussians per iteration: their alphas are independent
+      // and overlap; the decisions and accumulations then run in list order
       while (mask) {
         const int j1 = (int)__builtin_ctzll(mask);
         mask &= mask - 1;
         const bool has2 = mask != 0;
         const int j2 = has2 ? (int)__builtin_ctzll(mask) : j1;
         if (has2) mask &= mask - 1;
-        const float4 gs1 = cur.st[j1], qv1 = cur.cq[j1];
-        const float4 gs2 = cur.st[j2], qv2 = cur.cq[j2];
-        const float P1 = exponent(gs1, qv1, fpx, fpy);
-        const float P2 = exponent(gs2, qv2, fpx, fpy);
-        const float al1 = blend_alpha(gs1.z, P1);
-        const float al2 = blend_alpha(gs2.z, P2);
+        const float4 w1 = cur.wq[j1], w2 = cur.wq[j2];
+        const float2 c1 = *reinterpret_cast<const float2*>(&cur.st[j1]);
+        const float2 c2 = *reinterpret_cast<const float2*>(&cur.st[j2]);
+        const float al1 = blend_alpha(exponent(w1, c1.x, c1.y, fpx, fpy));
+        const float al2 = blend_alpha(exponent(w2, c2.x, c2.y, fpx, fpy));
         if (COUNT) wc.steps += has2 ? 2 : 1;
-        float wgt1, wgt2;
-        {
-          const bool pass = passes(P1 + dead, gs1.w);
-          if (COUNT && __builtin_amdgcn_ballot_w64(pass) != 0) ++wc.steps_pass;
-          const bool ok = pass & (al1 >= 1.f / 255.f);
-          const float Tn = T * (1.f - al1);
-          const bool stop = ok & (Tn < 1e-4f);
-          const bool blend = ok & !stop;
-          if (COUNT && stop) stop_pos = b0 + j1;
-          dead = stop ? INFINITY : dead;
-          wgt1 = blend ? al1 * T : 0.f;
-          T = blend ? Tn : T;
-          last = blend ? b0 + j1 : last;
-          if (COUNT && blend) ++wc.n_blend;
-        }
-        {
-          const bool pass = has2 & passes(P2 + dead, gs2.w);
-          if (COUNT && __builtin_amdgcn_ballot_w64(pass) != 0) ++wc.steps_pass;
-          const bool ok = pass & (al2 >= 1.f / 255.f);
-          const float Tn = T * (1.f - al2);
-          const bool stop = ok & (Tn < 1e-4f);
-          const bool blend = ok & !stop;
-          if (COUNT && stop) stop_pos = b0 + j2;
-          dead = stop ? INFINITY : dead;
-          wgt2 = blend ? al2 * T : 0.f;
-          T = blend ? Tn : T;
-          last = blend ? b0 + j2 : last;
-          if (COUNT && blend) ++wc.n_blend;
-        }
-        if (__builtin_amdgcn_ballot_w64(wgt1 > 0.f) != 0) {
-          if (COUNT) ++wc.steps_blend;
-          float fl[NM];
-          load_slice<NM>(cur.fe + j1 * C + NM * q4, fl);
-#pragma unroll
-          for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt1, fl[m], acc[m], 0, 0, 0);
-        }
-        if (__builtin_amdgcn_ballot_w64(wgt2 > 0.f) != 0) {
-          if (COUNT) ++wc.steps_blend;
-          float fl[NM];
-          load_slice<NM>(cur.fe + j2 * C + NM * q4, fl);
-#pragma unroll
-          for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt2, fl[m], acc[m], 0, 0, 0);
-        }
+        visit(cur, j1, b0 + j1, al1, true);
+        visit(cur, j2, b0 + j2, al2, has2);
       }
     }
     // ---- finish batch b+1: every wave's DMA complete, then its 2D state
     __builtin_amdgcn_s_waitcnt(0);
-    const int alive = __syncthreads_count(dead == 0.f);
+    const int alive = __syncthreads_count(amin < 1.f);
     if (more) {
-      if (tid < nb1) make_state(nxt.xy[tid], nxt.co[tid], ox, oy, nxt.st[tid], nxt.cq[tid]);
+      if (tid < nb1) stage_state<C, B>(nxt, tid, ox, oy);
       if (tid < B) cur.ix[tid] = pidx;
     }
     __syncthreads();

@@ -72,6 +72,8 @@ struct Slot {
   // workspace
   double2* xy = nullptr;
   float4* conic_o = nullptr;
+  float4* wq = nullptr;
+  float4* ext = nullptr;
   uint2* rect = nullptr;
   uint32_t* depth = nullptr;
   int32_t* tile_count = nullptr;
@@ -145,7 +147,7 @@ int64_t keys_est(const tg_server* s, int64_t n) {
 // workspace and its outputs
 int64_t footprint_of(const tg_server* s, const tg_request& r) {
   const int64_t px = (int64_t)r.cam.width * r.cam.height;
-  return tg::padded(r.g.n) * 44 + keys_est(s, r.g.n) * 20 + px * (8 + 4 * ((int64_t)s->opts.c + 1));
+  return tg::padded(r.g.n) * 76 + keys_est(s, r.g.n) * 20 + px * (8 + 4 * ((int64_t)s->opts.c + 1));
 }
 
 tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
@@ -154,6 +156,8 @@ tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
   b.hdr_dev = sl.hdr_dev;
   b.xy = sl.xy;
   b.conic_o = sl.conic_o;
+  b.wq = sl.wq;
+  b.ext = sl.ext;
   b.rect = sl.rect;
   b.depth = sl.depth;
   b.tile_count = sl.tile_count;
@@ -190,7 +194,7 @@ hipError_t enqueue_batch(const tg_server* s, const Slot& sl) {
 void free_slot(Slot& sl) {
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   if (sl.graph) (void)hipGraphDestroy(sl.graph);
-  void* d[] = {sl.xy, sl.conic_o, sl.rect, sl.depth, sl.tile_count, sl.tile_start, sl.tile_cursor,
+  void* d[] = {sl.xy, sl.conic_o, sl.wq, sl.ext, sl.rect, sl.depth, sl.tile_count, sl.tile_start, sl.tile_cursor,
                sl.tile_order,
                sl.keys, sl.keys_tmp, sl.sorted, sl.T_final, sl.last, sl.g2d, sl.dev, sl.table_dev,
                sl.hdr_dev};
@@ -209,7 +213,8 @@ bool alloc_slot(tg_server* s, Slot& sl) {
                px = (size_t)s->cap_pixels;
   bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-            dalloc(&sl.xy, g) && dalloc(&sl.conic_o, g) && dalloc(&sl.rect, g) && dalloc(&sl.depth, g) &&
+            dalloc(&sl.xy, g) && dalloc(&sl.conic_o, g) && dalloc(&sl.wq, g) && dalloc(&sl.ext, g) &&
+            dalloc(&sl.rect, g) && dalloc(&sl.depth, g) &&
             dalloc(&sl.tile_count, t) && dalloc(&sl.tile_start, t + 1) && dalloc(&sl.tile_cursor, t) &&
             dalloc(&sl.tile_order, t) &&
             dalloc(&sl.keys, k) && dalloc(&sl.keys_tmp, k) && dalloc(&sl.sorted, k) &&

@@ -22,6 +22,8 @@ struct tg_frame {
   int32_t max_w = 0, max_h = 0, max_tiles = 0;
   double2* xy = nullptr;
   float4* conic_o = nullptr;
+  float4* wq = nullptr;
+  float4* ext = nullptr;
   uint2* rect = nullptr;
   uint32_t* depth = nullptr;
   int32_t* tile_count = nullptr;
@@ -76,7 +78,7 @@ tg_status dalloc(T** p, size_t count) {
 }
 
 void free_frame(tg_frame* f) {
-  void* ptrs[] = {f->xy, f->conic_o, f->rect, f->depth, f->tile_count, f->tile_start,
+  void* ptrs[] = {f->xy, f->conic_o, f->wq, f->ext, f->rect, f->depth, f->tile_count, f->tile_start,
                   f->tile_cursor, f->tile_order, f->keys, f->keys_tmp, f->sorted, f->T_final,
                   f->last, f->g2d, f->dev};
   for (void* p : ptrs)
@@ -104,6 +106,8 @@ tg::BatchArgs frame_args(tg_frame* f) {
   b.hdr.g_end = tg::padded(f->n);
   b.xy = f->xy;
   b.conic_o = f->conic_o;
+  b.wq = f->wq;
+  b.ext = f->ext;
   b.rect = f->rect;
   b.depth = f->depth;
   b.tile_count = f->tile_count;
@@ -178,6 +182,8 @@ tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max
   tg_status st = TG_OK;
   if (st == TG_OK) st = dalloc(&f->xy, f->g_cap);
   if (st == TG_OK) st = dalloc(&f->conic_o, f->g_cap);
+  if (st == TG_OK) st = dalloc(&f->wq, f->g_cap);
+  if (st == TG_OK) st = dalloc(&f->ext, f->g_cap);
   if (st == TG_OK) st = dalloc(&f->rect, f->g_cap);
   if (st == TG_OK) st = dalloc(&f->depth, f->g_cap);
   if (st == TG_OK) st = dalloc(&f->tile_count, f->max_tiles);

@@ -12,6 +12,11 @@
 //   per Gaussian  xy      double2  projected mean (u, v) in pixels, FP64 so
 //                                  that the render's pixel offsets are exact
 //                 conic_o float4   (A, B, C, opacity); conic = Sigma'^-1
+//                 wq      float4   exponent factors (s, s k, r, log2 o): the
+//                                  exponent of the opacity-weighted Gaussian
+//                                  is log2 o - (s (dx + k dy))^2 - (r dy)^2
+//                 ext     float4   (ex, ey, opacity, 0): half-extents of the
+//                                  alpha >= 1/255 ellipse (-inf: none)
 //                 rect    uint2    tile rectangle, x0 | x1 << 16, y0 | y1 << 16
 //                                  (empty: x0 > x1)
 //                 depth   uint32   IEEE bits of the float32 view depth
@@ -104,6 +109,8 @@ struct BatchArgs {
   // workspace
   double2* xy;
   float4* conic_o;
+  float4* wq;
+  float4* ext;
   uint2* rect;
   uint32_t* depth;
   int32_t* tile_count;
