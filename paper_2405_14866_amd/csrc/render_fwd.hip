@@ -15,9 +15,10 @@
 //     batch loop is unrolled by two, so the compiler can tell the DMA target
 //     from the buffer being walked and the walk never waits for the DMA;
 //     each wave waits for its own DMA before the barrier that ends the batch;
-//   * the kernel asks for six waves per SIMD: latency, not issue, bounds the
-//     walk, and the few loop-invariant values that do not fit are kept in
-//     scratch outside the walk;
+//   * the kernel asks for five waves per SIMD: latency, not issue, bounds
+//     the walk, and the registers of five waves leave room to fetch both
+//     entries' feature slices at the top of a walk iteration, so that their
+//     LDS latency overlaps the exponents and decisions;
 //   * per staged Gaussian the walk reads the projection's exponent factors
 //     (s, s k, r, log2 o) and the tile-dependent offsets (c1, c2), formed in
 //     FP64 from the FP64 mean relative to the tile origin (so pixel offsets
@@ -60,13 +61,15 @@ constexpr int RENDER_B = 64;             // Gaussians per staged batch
 constexpr int PERSISTENT_WG = 256 * 8;   // persistent workgroups (>= resident capacity)
 
 
-// this lane's C/4 contiguous features of a row (LDS), for the MFMA B operands
+// this lane's C/4 contiguous features of a row (LDS), for the MFMA B
+// operands; volatile LDS reads, so that they issue where they are written
+// and are not sunk into the branches that consume them
 template <int NM>
 __device__ __forceinline__ void load_slice(const float* p, float (&fl)[NM]) {
   if constexpr (NM % 4 == 0) {
 #pragma unroll
     for (int k = 0; k < NM / 4; ++k) {
-      const float4 v = reinterpret_cast<const float4*>(p)[k];
+      const f4v v = ((const volatile __attribute__((address_space(3))) f4v*)p)[k];
       fl[4 * k] = v.x; fl[4 * k + 1] = v.y; fl[4 * k + 2] = v.z; fl[4 * k + 3] = v.w;
     }
   } else {
@@ -183,7 +186,7 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   // alpha: the stop / blend decisions, then the state updates and the
   // feature accumulation, each behind a wave-uniform branch (a pixel ends
   // at most once, and most steps blend in only some of the pixels).
-  auto visit = [&](const BatchLDS<C, B>& cur, int j, int pos, float al, bool valid) {
+  auto visit = [&](const float (&fl)[NM], int pos, float al, bool valid) {
     const bool ok = valid & (al >= amin);
     const float Tn = __builtin_fmaf(-al, T, T);
     const bool stop = ok & (Tn < 1e-4f);
@@ -199,8 +202,6 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
       const float wgt = blend ? al * T : 0.f;
       T = blend ? Tn : T;
       last = blend ? pos : last;
-      float fl[NM];
-      load_slice<NM>(cur.fe + j * C + NM * q4, fl);
 #pragma unroll
       for (int m = 0; m < NM; ++m) acc[m] = __builtin_amdgcn_mfma_f32_4x4x1f32(wgt, fl[m], acc[m], 0, 0, 0);
     }
@@ -229,14 +230,18 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
         const bool has2 = mask != 0;
         const int j2 = has2 ? (int)__builtin_ctzll(mask) : j1;
         if (has2) mask &= mask - 1;
+        // feature slices of both entries first (see load_slice)
+        float fl1[NM], fl2[NM];
+        load_slice<NM>(cur.fe + j1 * C + NM * q4, fl1);
+        load_slice<NM>(cur.fe + j2 * C + NM * q4, fl2);
         const float4 w1 = cur.wq[j1], w2 = cur.wq[j2];
         const float2 c1 = *reinterpret_cast<const float2*>(&cur.st[j1]);
         const float2 c2 = *reinterpret_cast<const float2*>(&cur.st[j2]);
         const float al1 = blend_alpha(exponent(w1, c1.x, c1.y, fpx, fpy));
         const float al2 = blend_alpha(exponent(w2, c2.x, c2.y, fpx, fpy));
         if (COUNT) wc.steps += has2 ? 2 : 1;
-        visit(cur, j1, b0 + j1, al1, true);
-        visit(cur, j2, b0 + j2, al2, has2);
+        visit(fl1, b0 + j1, al1, true);
+        visit(fl2, b0 + j2, al2, has2);
       }
     }
     // ---- finish batch b+1: every wave's DMA complete, then its 2D state
@@ -301,7 +306,7 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
 // serving batch) rather than inline (a single render); the two are separate
 // instantiations so that each keeps its own launch statistics.
 template <int C, int B, bool COUNT, bool TABLE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_render(BatchArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_render(BatchArgs a) {
   if (a.dev->overflow) return;
   if (!TABLE) a.table = nullptr;
   const BatchHdr h = batch_hdr(a);
