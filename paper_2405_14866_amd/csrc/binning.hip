@@ -110,28 +110,39 @@ __device__ __forceinline__ int order_bucket(int32_t count) {
   return ORDER_BUCKETS - 1 - min(count >> ORDER_SHIFT, ORDER_BUCKETS - 1);
 }
 
+// inclusive scan over the 64 lanes of a wave
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
 __global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
-  __shared__ int64_t part[1024];
+  __shared__ int64_t wsum[16];
   __shared__ int32_t bucket[ORDER_BUCKETS];
   const BatchHdr h = batch_hdr(a);
   const int nt = h.n_tiles;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int per = (nt + 1023) / 1024;
   const int b = min(nt, tid * per), e = min(nt, b + per);
   if (tid < ORDER_BUCKETS) bucket[tid] = 0;
   int64_t sum = 0;
   for (int t = b; t < e; ++t) sum += a.tile_count[t];
-  part[tid] = sum;
+  const int64_t incl = wave_incl_scan(sum, lane);
+  if (lane == 63) wsum[wv] = incl;
   __syncthreads();
   for (int t = b; t < e; ++t) atomicAdd(&bucket[order_bucket(a.tile_count[t])], 1);
-  for (int off = 1; off < 1024; off <<= 1) {   // Hillis-Steele inclusive scan
-    const int64_t v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  int64_t run = incl - sum, total = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t v = wsum[k];
+    run += k < wv ? v : 0;
+    total += v;
   }
-  int64_t run = part[tid] - sum;
-  const int64_t total = part[1023];
   const bool over = total > a.key_cap;
   for (int t = b; t < e; ++t) {
     const int32_t v = over ? 0 : (int32_t)run;
@@ -144,13 +155,10 @@ __global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
     a.dev->n_keys = total;
     a.dev->overflow = over ? 1 : 0;
   }
-  if (tid == 0) {                               // bucket sizes -> first positions
-    int32_t acc = 0;
-    for (int k = 0; k < ORDER_BUCKETS; ++k) {
-      const int32_t c = bucket[k];
-      bucket[k] = acc;
-      acc += c;
-    }
+  __syncthreads();
+  if (tid < ORDER_BUCKETS) {                    // bucket sizes -> first positions
+    const int32_t c = bucket[tid];
+    bucket[tid] = wave_incl_scan(c, lane) - c;
   }
   __syncthreads();
   // positions inside a bucket are taken in arrival order; the blend of a

@@ -135,11 +135,12 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
     const double ty = (double)c.R[3] * X + (double)c.R[4] * Y + (double)c.R[5] * Z + (double)c.t[1];
     const double tz = (double)c.R[6] * X + (double)c.R[7] * Y + (double)c.R[8] * Z + (double)c.t[2];
     const double fx = c.fx, fy = c.fy;
-    xy.x = fx * tx / tz + (double)c.cx;
-    xy.y = fy * ty / tz + (double)c.cy;
+    const double itz = 1.0 / tz;
+    xy.x = fx * tx * itz + (double)c.cx;
+    xy.y = fy * ty * itz + (double)c.cy;
     const double dw = qw, dx = qx, dy = qy, dz = qz;
-    const double nq = sqrt(dw * dw + dx * dx + dy * dy + dz * dz);
-    const double w = dw / nq, x = dx / nq, y = dy / nq, z = dz / nq;
+    const double inq = 1.0 / sqrt(dw * dw + dx * dx + dy * dy + dz * dz);
+    const double w = dw * inq, x = dx * inq, y = dy * inq, z = dz * inq;
     double Rq[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
                        {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
                        {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
     for (int p = 0; p < 3; ++p)
       for (int k = 0; k < 3; ++k)
         S[p][k] = Rq[p][0] * s2[0] * Rq[k][0] + Rq[p][1] * s2[1] * Rq[k][1] + Rq[p][2] * s2[2] * Rq[k][2];
-    const double j00 = fx / tz, j02 = -fx * tx / (tz * tz), j11 = fy / tz, j12 = -fy * ty / (tz * tz);
+    const double j00 = fx * itz, j02 = -fx * tx * itz * itz, j11 = fy * itz, j12 = -fy * ty * itz * itz;
     double A[2][3];
     for (int k = 0; k < 3; ++k) {
       A[0][k] = j00 * (double)c.R[k] + j02 * (double)c.R[6 + k];
@@ -162,12 +163,13 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
     const double sc = AS[1][0] * A[1][0] + AS[1][1] * A[1][1] + AS[1][2] * A[1][2] + 0.3;
     const double det = sa * sc - sb * sb;
     if (det > 0.0) {
-      co = make_float4((float)(sc / det), (float)(-sb / det), (float)(sa / det), op);
+      const double idet = 1.0 / det, isc = 1.0 / sc;
+      co = make_float4((float)(sc * idet), (float)(-sb * idet), (float)(sa * idet), op);
       constexpr double L2E = 1.4426950408889634;
-      const double sw = sqrt(0.5 * L2E * sc / det);
-      wq = make_float4((float)sw, (float)(sw * (-sb / sc)), (float)sqrt(0.5 * L2E / sc), (float)log2((double)op));
-      if ((double)op * 255.0 >= 1.0) {
-        const double rho = 2.0 * log(255.0 * (double)op);
+      const double sw = sqrt(0.5 * L2E * sc * idet);
+      wq = make_float4((float)sw, (float)(sw * (-sb * isc)), (float)sqrt(0.5 * L2E * isc), log2f(op));
+      if (op * 255.f >= 1.f) {
+        const double rho = 2.0 * (double)logf(255.f * op);
         ext.x = (float)sqrt(rho * sa);
         ext.y = (float)sqrt(rho * sc);
       }
