@@ -38,6 +38,10 @@ namespace {
 
 constexpr int BWD_B = 64;      // Gaussians per staged batch
 constexpr int GROUP = 16;      // Gaussians per matrix-core reduction
+// LDS row of one group Gaussian's 64 pixel values, padded by 4 floats: the
+// matrix-core operand reads take one row per lane column (16 rows at once),
+// and an unpadded 64-float stride would put all of them on the same banks
+constexpr int ROW = 68;
 
 template <int C>
 struct BwdShared {
@@ -50,9 +54,9 @@ struct BwdShared {
   int32_t wl[4][BWD_B];        // per wave: reaching batch entries, last first
   // per wave, row i of the group: pixel values in k-block order, p = 4 kb + q
   // stored at q * 16 + kb (so one lane's 16 A operands are contiguous)
-  __align__(16) float wa[4][GROUP * 64];
-  __align__(16) float dp[4][GROUP * 64];
-  float mom[4][GROUP][8];
+  __align__(16) float wa[4][GROUP * ROW];
+  __align__(16) float dp[4][GROUP * ROW];
+  float mom[4][GROUP][9];      // 9: rows on distinct banks for the per-row reads
   int32_t smax;
 };
 
@@ -201,8 +205,8 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
             T = contrib ? Ti : T;
           }
         }
-        sh.wa[w][i * 64 + perm64(lane)] = wv;
-        sh.dp[w][i * 64 + perm64(lane)] = dv;
+        sh.wa[w][i * ROW + perm64(lane)] = wv;
+        sh.dp[w][i * ROW + perm64(lane)] = dv;
       }
       if (cmask == 0) continue;
       __builtin_amdgcn_wave_barrier();
@@ -210,8 +214,8 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
       f4v accF[NB], accM = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int nb2 = 0; nb2 < NB; ++nb2) accF[nb2] = f4v{0.f, 0.f, 0.f, 0.f};
-      const f4v* wrow = reinterpret_cast<const f4v*>(&sh.wa[w][l16 * 64 + ql * 16]);
-      const f4v* drow = reinterpret_cast<const f4v*>(&sh.dp[w][l16 * 64 + ql * 16]);
+      const f4v* wrow = reinterpret_cast<const f4v*>(&sh.wa[w][l16 * ROW + ql * 16]);
+      const f4v* drow = reinterpret_cast<const f4v*>(&sh.dp[w][l16 * ROW + ql * 16]);
 #pragma unroll
       for (int k4 = 0; k4 < 4; ++k4) {
         const f4v av = wrow[k4], dvv = drow[k4];
