@@ -37,9 +37,9 @@
 //     independent and overlap, then their decisions and feature
 //     accumulations run in list order.  A pixel's threshold test is one
 //     compare against its own minimum alpha (1/255 while it runs, 2 once it
-//     has ended, so an ended pixel fails every later test); the end of a
-//     pixel and the state updates of a blend sit behind wave-uniform
-//     branches, since a pixel ends once and many steps blend in few pixels;
+//     has ended, so an ended pixel fails every later test); the state
+//     updates of a blend and its feature accumulation sit behind a
+//     wave-uniform branch, since many steps blend in few pixels;
 //   * the feature accumulation of a step is the rank-1 update F += w f^T of
 //     the wave's 64 pixels x C channels (w: each lane's blend weight, 0 where
 //     it does not blend).  It runs on the matrix cores as C/4
@@ -182,19 +182,17 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   if (tid < B && tid < len) stage_state<C, B>(L0, tid, ox, oy);
   __syncthreads();
 
-  // One list entry j (position pos) against this wave's pixels, given its
-  // alpha: the stop / blend decisions, then the state updates and the
-  // feature accumulation, each behind a wave-uniform branch (a pixel ends
-  // at most once, and most steps blend in only some of the pixels).
+  // One list entry (position pos) against this wave's pixels, given its
+  // alpha and feature slice: the stop / blend decisions, then the state
+  // updates and the feature accumulation behind a wave-uniform branch
+  // (most steps blend in only some of the pixels).
   auto visit = [&](const float (&fl)[NM], int pos, float al, bool valid) {
     const bool ok = valid & (al >= amin);
     const float Tn = __builtin_fmaf(-al, T, T);
     const bool stop = ok & (Tn < 1e-4f);
     if (COUNT && __builtin_amdgcn_ballot_w64(ok) != 0) ++wc.steps_pass;
-    if (__builtin_amdgcn_ballot_w64(stop) != 0) {
-      amin = stop ? 2.f : amin;
-      if (COUNT && stop) stop_pos = pos;
-    }
+    amin = stop ? 2.f : amin;
+    if (COUNT && stop) stop_pos = pos;
     const bool blend = ok & !stop;
     if (__builtin_amdgcn_ballot_w64(blend) != 0) {
       if (COUNT) ++wc.steps_blend;
