@@ -121,21 +121,29 @@ __device__ __forceinline__ T wave_incl_scan(T x, int lane) {
   return x;
 }
 
-__global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
-  __shared__ int64_t wsum[16];
-  __shared__ int32_t bucket[ORDER_BUCKETS];
-  const BatchHdr h = batch_hdr(a);
-  const int nt = h.n_tiles;
+// The scan of one workgroup over the tile counts, each lane owning PER
+// consecutive tiles; when PER is a compile-time bound the lane's counts are
+// read once into registers (all loads in flight together).
+template <int KMAX>
+__device__ __forceinline__ void scan_tiles(const BatchArgs& a, int nt, int per, int64_t* wsum, int32_t* bucket) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int per = (nt + 1023) / 1024;
   const int b = min(nt, tid * per), e = min(nt, b + per);
-  if (tid < ORDER_BUCKETS) bucket[tid] = 0;
+  const int m = e - b;
+  int32_t cnt[KMAX > 0 ? KMAX : 1];
+  auto count = [&](int k) -> int32_t { return KMAX > 0 ? cnt[k] : a.tile_count[b + k]; };
+  if constexpr (KMAX > 0) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) cnt[k] = k < m ? a.tile_count[b + k] : 0;
+  }
+  const int mm = KMAX > 0 ? KMAX : m;         // loop bound (the cached counts beyond m are zero)
   int64_t sum = 0;
-  for (int t = b; t < e; ++t) sum += a.tile_count[t];
+#pragma unroll
+  for (int k = 0; k < mm; ++k) if (k < m) sum += count(k);
   const int64_t incl = wave_incl_scan(sum, lane);
   if (lane == 63) wsum[wv] = incl;
   __syncthreads();
-  for (int t = b; t < e; ++t) atomicAdd(&bucket[order_bucket(a.tile_count[t])], 1);
+#pragma unroll
+  for (int k = 0; k < mm; ++k) if (k < m) atomicAdd(&bucket[order_bucket(count(k))], 1);
   int64_t run = incl - sum, total = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -144,11 +152,14 @@ __global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
     total += v;
   }
   const bool over = total > a.key_cap;
-  for (int t = b; t < e; ++t) {
-    const int32_t v = over ? 0 : (int32_t)run;
-    a.tile_start[t] = v;
-    a.tile_cursor[t] = v;
-    run += a.tile_count[t];
+#pragma unroll
+  for (int k = 0; k < mm; ++k) {
+    if (k < m) {
+      const int32_t v = over ? 0 : (int32_t)run;
+      a.tile_start[b + k] = v;
+      a.tile_cursor[b + k] = v;
+      run += count(k);
+    }
   }
   if (tid == 1023) {
     a.tile_start[nt] = over ? 0 : (int32_t)total;
@@ -163,7 +174,19 @@ __global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
   __syncthreads();
   // positions inside a bucket are taken in arrival order; the blend of a
   // tile does not depend on when it runs
-  for (int t = b; t < e; ++t) a.tile_order[atomicAdd(&bucket[order_bucket(a.tile_count[t])], 1)] = t;
+#pragma unroll
+  for (int k = 0; k < mm; ++k)
+    if (k < m) a.tile_order[atomicAdd(&bucket[order_bucket(count(k))], 1)] = b + k;
+}
+
+__global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
+  __shared__ int64_t wsum[16];
+  __shared__ int32_t bucket[ORDER_BUCKETS];
+  const int nt = batch_hdr(a).n_tiles;
+  const int per = (nt + 1023) / 1024;
+  if (threadIdx.x < ORDER_BUCKETS) bucket[threadIdx.x] = 0;
+  if (per <= 8) scan_tiles<8>(a, nt, per, wsum, bucket);
+  else scan_tiles<0>(a, nt, per, wsum, bucket);
 }
 
 // Scatter of one chunk's keys into the tile segments: LDS counts, one
