@@ -74,12 +74,13 @@ def test_alone_equals_in_the_mix(use_graph):
     assert bitwise
 
 
-def test_served_request_matches_oracle():
+@pytest.mark.parametrize("c", [8, 64])
+def test_served_request_matches_oracle(c):
     torch = torch_cuda()
     from paper_2405_14866_amd.serve import Server
-    reqs = _requests(3, c=8, seed=300)
-    bg = np.linspace(-1, 1, 8).astype(np.float32)
-    srv = Server(0, c=8, slots=1, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=600000,
+    reqs = _requests(3, c=c, seed=300)
+    bg = np.linspace(-1, 1, c).astype(np.float32)
+    srv = Server(0, c=c, slots=1, max_batch=3, max_gauss_per_batch=60000, max_keys_per_batch=600000,
                  max_pixels_per_batch=3 * 128 * 128, max_side=128, batch_window_us=200000)
     served, results = _served(srv, reqs, torch, bg=torch.as_tensor(bg, device="cuda"))
     srv.close()
