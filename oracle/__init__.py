@@ -48,7 +48,7 @@ def _load():
     lib.tgo_render_brute.argtypes = [P, P, P, P]
     lib.tgo_pixel_walk.restype = ct.c_int
     lib.tgo_pixel_walk.argtypes = [P, ct.c_int, ct.c_int, P, ct.c_int]
-    lib.tgo_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P]
+    lib.tgo_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
     lib.tgo_fd.argtypes = [P, P, P, P, ct.c_int64, P, ct.c_double, P, P]
     _lib = lib
     return lib
@@ -177,14 +177,20 @@ class Oracle:
         return dict(feat=F, alpha=A)
 
     # ---------------------------------------------------------- backward
-    def backward(self, d_feat, d_alpha=None, bg=None):
-        """Analytic FP64 gradients w.r.t. the raw parameters.
+    def backward(self, d_feat, d_alpha=None, bg=None, flip_mask=None):
+        """Analytic FP64 gradients w.r.t. the raw parameters.  flip_mask
+        [H, W] uint8 (optional): per pixel, which near-threshold decisions
+        to invert, as the index of a pixel_variants variant.
 
         Returns dict(g2d [n, 6] (du, dv, dA, dB, dC, d_opacity), mean [3, n],
         log_scale [3, n], quat [4, n], opacity_logit [n], feat [n, c])."""
         bg = self.bg if bg is None else _f64(bg)
         dF = _f64(d_feat)
         dA = None if d_alpha is None else _f64(d_alpha)
+        fm = None
+        if flip_mask is not None:
+            fm = np.ascontiguousarray(flip_mask, np.uint8)
+            assert fm.shape == (self.H, self.W), fm.shape
         n, c = self.n, self.c
         out = dict(g2d=np.empty((n, 6)), mean=np.empty((3, n)),
                    log_scale=np.empty((3, n)), quat=np.empty((4, n)),
@@ -192,7 +198,7 @@ class Oracle:
         _load().tgo_render_bwd(self._h, _p(bg), _p(dF), _p(dA), _p(out["g2d"]),
                                _p(out["mean"]), _p(out["log_scale"]),
                                _p(out["quat"]), _p(out["opacity_logit"]),
-                               _p(out["feat"]))
+                               _p(out["feat"]), _p(fm))
         return out
 
     def finite_differences(self, sel, d_feat, d_alpha=None, eps=1e-6, bg=None):

@@ -29,7 +29,8 @@
 //
 // Near the two thresholds (alpha vs 1/255, T' vs 1e-4) an FP32 renderer may
 // legitimately take the other branch.  The oracle flags such decisions and
-// can evaluate the pixel under both branches (tgo_pixel_variants).
+// can evaluate the pixel under both branches (tgo_pixel_variants), and its
+// backward can differentiate a pixel under a chosen branch.
 //
 // Parity pins: see tests/test_oracle_pins.py (closed forms, invariants,
 // brute force on tiny scenes, finite differences for the backward).
@@ -725,9 +726,12 @@ void tgo_render_brute(void* h, const double* bg, double* out_feat, double* out_a
 // NULL.  Outputs: g2d [n][6] (du, dv, dA, dB, dC, d opacity), and the raw
 // parameter gradients g_mean [3][n], g_logscale [3][n], g_quat [4][n],
 // g_logit [n], g_feat [n][c].  Any output pointer may be NULL.
+// flip_mask [H][W] or NULL: bit b of a pixel's mask inverts the b-th
+// near-threshold decision of its walk, numbered as tgo_pixel_variants numbers
+// them (variant m of that call is mask m); a zero mask is the plain walk.
 void tgo_render_bwd(void* h, const double* bg, const double* d_img, const double* d_alpha,
                     double* g2d_out, double* g_mean, double* g_ls, double* g_quat, double* g_logit,
-                    double* g_feat) {
+                    double* g_feat, const uint8_t* flip_mask) {
   Ctx& k = *static_cast<Ctx*>(h);
   const int W = k.cam.W, H = k.cam.H, C = k.c;
   const int64_t T = (int64_t)k.tiles_x * k.tiles_y;
@@ -746,6 +750,7 @@ void tgo_render_bwd(void* h, const double* bg, const double* d_img, const double
       tgf[j].assign((size_t)len * C, 0.0);
       std::vector<double> F(C), g(C);
       std::vector<Contrib> cb;
+      std::vector<int> flip;
       for (int py = ty * TILE; py < std::min(H, ty * TILE + TILE); ++py)
         for (int px = tx * TILE; px < std::min(W, tx * TILE + TILE); ++px) {
           const int64_t pix = (int64_t)py * W + px;
@@ -756,6 +761,17 @@ void tgo_render_bwd(void* h, const double* bg, const double* d_img, const double
           PixelRun run;
           BlendOpts op;
           op.contrib = &cb;
+          const unsigned m = flip_mask ? flip_mask[pix] : 0u;
+          if (m) {   // the plain walk numbers the flagged decisions
+            PixelRun probe;
+            blend_pixel(k, k.proj.data(), k.list.data() + s, len, px + 0.5, py + 0.5, F.data(),
+                        probe);
+            std::fill(F.begin(), F.end(), 0.0);
+            flip.clear();
+            for (int b = 0; b < (int)probe.flags.size() && b < 8; ++b)
+              if (m & (1u << b)) flip.push_back(probe.flags[b].pos);
+            op.flip = &flip;
+          }
           blend_pixel(k, k.proj.data(), k.list.data() + s, len, px + 0.5, py + 0.5, F.data(), run,
                       op);
           pixel_adjoint(k, cb, run.T, g.data(), gA, bgp, k.proj.data(), tg2[j].data(),

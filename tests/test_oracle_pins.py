@@ -339,3 +339,30 @@ def test_analytic_feature_gradient_is_weight_sum(cfg1):
     r = o.render()
     assert abs(g["feat"][:, 0].sum() - r["alpha"].sum()) < 1e-9
     assert np.all(g["feat"][:, 1:] == 0)
+
+
+def test_backward_under_a_chosen_branch(cfg1):
+    """The backward of a pixel evaluated under another branch of its
+    near-threshold decisions differentiates that branch's image: with
+    dL/dF = 1 at that pixel only, the feature gradient of Gaussian i is its
+    blending weight alpha_i T_i in that branch, so sum_i g_i f_i reproduces
+    the branch's F (given by pixel_variants) in every channel, and the
+    gradients of the branches differ.  A zero mask is the plain backward."""
+    o = oracle.Oracle(cfg1)
+    r = o.render()
+    y, x = (int(v) for v in np.argwhere(r["nflags"] > 0)[0])
+    var = o.pixel_variants(x, y)
+    assert var is not None and len(var) >= 2
+    dF = np.zeros((cfg1.c, 64, 64)); dF[:, y, x] = 1.0
+    f = np.asarray(cfg1.feat, np.float64)
+    plain = o.backward(dF)
+    feats = []
+    for m in range(len(var)):
+        mask = np.zeros((64, 64), np.uint8); mask[y, x] = m
+        g = o.backward(dF, flip_mask=mask)
+        np.testing.assert_allclose((g["feat"] * f).sum(0), var[m, :-1], rtol=1e-12, atol=1e-15)
+        feats.append(g["feat"])
+        if m == 0:
+            for k in ("g2d", "feat", "mean", "quat"):
+                assert np.array_equal(g[k], plain[k]), k
+    assert np.abs(feats[1] - feats[0]).max() > 1e-6
