@@ -162,7 +162,7 @@ tg_status tg_frame_work(tg_frame* frame, int64_t* counts, int32_t n_counts);
  * tg_render_fwd of this frame and recomputes every earlier transmittance by
  * walking each pixel's list backwards.  Writes the raw-parameter gradients
  * of `out` (overwritten, device pointers; any of them may be NULL except
- * d_feat). */
+ * d_feat, which may be NULL only when g->n == 0). */
 tg_status tg_render_bwd(tg_frame* frame, const tg_gaussians* g, const float* bg,
                         const float* d_feat, const float* d_alpha, const tg_grads* out,
                         void* stream);

@@ -301,10 +301,11 @@ tg_status tg_frame_work(tg_frame* f, int64_t* counts, int32_t n_counts) {
 
 tg_status tg_render_bwd(tg_frame* f, const tg_gaussians* g, const float* bg, const float* d_feat,
                         const float* d_alpha, const tg_grads* out, void* stream) {
-  if (!f || !f->rendered || !d_feat || !out || !out->d_feat) return TG_ERR_INVALID;
+  if (!f || !f->rendered || !d_feat || !out) return TG_ERR_INVALID;
   tg_status st = check_gaussians(f, g, true);
   if (st != TG_OK) return st;
   if (g->n != f->n || g->c != f->c) return TG_ERR_INVALID;
+  if (g->n > 0 && !out->d_feat) return TG_ERR_INVALID;   // an empty set has no feature gradients
   DeviceGuard guard(f->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   f->last_stream = s;

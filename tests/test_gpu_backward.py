@@ -56,6 +56,39 @@ def test_backward_channel_counts(c):
     _run(sc, dF)
 
 
+def test_ragged_body_scene_backward():
+    """The adjoint on a 72x40 target (partial tiles on two borders), C = 16,
+    with dL/dalpha."""
+    sc = scenes.make_body_scene(7, 48, 66.0, 16, 72, 132.0)
+    cam = scenes.Camera(sc.cam.R, sc.cam.t, sc.cam.fx, sc.cam.fy, 36.0, 20.0, 72, 40)
+    sc = sc.with_cam(cam)
+    rng = np.random.default_rng(8)
+    dF = rng.standard_normal((16, 40, 72)).astype(np.float32)
+    dA = rng.standard_normal((40, 72)).astype(np.float32)
+    print("ragged", _run(sc, dF, dA))
+
+
+def test_backward_where_nothing_blends(cfg1):
+    """An empty set, a set entirely behind the camera and a set of opacity 0
+    (every pair skipped): the adjoint runs and every gradient is exactly 0."""
+    torch = torch_cuda()
+    cam = scenes.Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), 64.0, 64.0, 32.0, 32.0,
+                        64, 64)
+    empty = scenes.Scene(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros((4, 0)), np.zeros(0),
+                         np.zeros((0, 8)), cam)
+    behind = scenes.single_gaussian_scene(np.array([[0, 0, -1.0], [0, 0, 0.1]]).T, 0.05, c=8, cam=cam)
+    clear = scenes.Scene(cfg1.mean, cfg1.scale, cfg1.quat, np.zeros(cfg1.n), cfg1.feat, cfg1.cam)
+    dF = torch.ones((8, 64, 64), device="cuda")
+    for sc in (empty, behind, clear):
+        gpu, rast, g = gpu_render(sc, lists=False)
+        assert np.all(gpu["alpha"] == 0)
+        gr = rast.backward(g, dF, torch.ones((64, 64), device="cuda"))
+        torch.cuda.synchronize()
+        for k, v in gr.items():
+            assert v.numel() == (0 if sc.n == 0 else v.numel()), k
+            assert torch.count_nonzero(v).item() == 0, (sc.name, k)
+
+
 def test_autograd_function_matches_oracle(cfg1):
     """rasterize() as a torch.autograd.Function: gradients w.r.t. the raw
     parameters in [N, k] layout."""
