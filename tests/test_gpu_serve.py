@@ -91,6 +91,51 @@ def test_served_request_matches_oracle(c):
                         bg=bg.astype(np.float64), check_last=False)
 
 
+def test_degenerate_requests_in_the_mix():
+    """An empty request, one whose Gaussians are all behind the camera and
+    one on a ragged 72x40 target, batched with two ordinary requests and a
+    non-black background: every result equals its plain render bit for bit,
+    the first two are the background with alpha 0, and the ragged one
+    matches the oracle."""
+    torch = torch_cuda()
+    from paper_2405_14866_amd.rasterize import GaussianSoA, Rasterizer
+    from paper_2405_14866_amd.serve import Server
+    c = 32
+    cam = scenes.Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), 64.0, 64.0, 32.0, 32.0,
+                        64, 64)
+    empty = scenes.Scene(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros((4, 0)), np.zeros(0),
+                         np.zeros((0, c)), cam)
+    behind = scenes.single_gaussian_scene(np.array([[0, 0, -1.0], [0, 0, 0.1]]).T, 0.05, c=c, cam=cam)
+    body = scenes.make_body_scene(7, 48, 66.0, c, 72, 132.0)
+    ragged = body.with_cam(scenes.Camera(body.cam.R, body.cam.t, body.cam.fx, body.cam.fy, 36.0, 20.0,
+                                         72, 40))
+    reqs = [_requests(1, c=c, seed=400)[0], empty, ragged, behind, _requests(1, c=c, seed=401)[0]]
+    bg = np.linspace(-0.5, 0.5, c).astype(np.float32)
+    bgt = torch.as_tensor(bg, device="cuda")
+    plain = []
+    for sc in reqs:
+        r = Rasterizer(0, max_n=max(1, sc.n), max_w=sc.cam.width, max_h=sc.cam.height)
+        f, a = r.forward(GaussianSoA.from_scene(sc), sc.cam, bgt)
+        plain.append((f.cpu().numpy(), a.cpu().numpy()))
+    srv = Server(0, c=c, slots=1, max_batch=len(reqs), max_gauss_per_batch=60000,
+                 max_keys_per_batch=600000, max_pixels_per_batch=len(reqs) * 128 * 128, max_side=128,
+                 batch_window_us=200000)
+    served, results = _served(srv, reqs, torch, bg=bgt)
+    srv.close()
+    assert all(r.status == 0 for r in results), [r.status for r in results]
+    print("batch sizes", [r.batch_size for r in results])
+    assert max(r.batch_size for r in results) > 1
+    for (fp, ap), (fs, as_) in zip(plain, served):
+        assert np.array_equal(fp, fs) and np.array_equal(ap, as_)
+    for k in (1, 3):
+        f, a = served[k]
+        assert np.all(a == 0)
+        np.testing.assert_array_equal(f, np.broadcast_to(bg[:, None, None], f.shape))
+    f, a = served[2]
+    compare_forward(dict(feat=f, alpha=a), oracle.Oracle(ragged), bg=bg.astype(np.float64),
+                    check_last=False)
+
+
 def _last_placeholder(ora, sc, bg):
     return np.zeros((sc.cam.height, sc.cam.width), np.int32)
 
