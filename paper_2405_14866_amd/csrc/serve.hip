@@ -517,10 +517,17 @@ tg_status tg_serve_wait(tg_server* s, uint64_t ticket, tg_result* out) {
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->tickets.find(ticket);
   if (it == s->tickets.end()) return TG_ERR_NOT_FOUND;
-  s->done_cv.wait(lk, [&] { return s->tickets[ticket].status != TG_PENDING; });
-  const Ticket& t = s->tickets[ticket];
-  fill_result(t, out);
-  return (tg_status)t.status;
+  // another caller may release the ticket while this one waits: look it up
+  // afresh on every wake-up (operator[] would re-create it as pending)
+  const Ticket* t = nullptr;
+  s->done_cv.wait(lk, [&] {
+    auto j = s->tickets.find(ticket);
+    t = j == s->tickets.end() ? nullptr : &j->second;
+    return !t || t->status != TG_PENDING;
+  });
+  if (!t) return TG_ERR_NOT_FOUND;
+  fill_result(*t, out);
+  return (tg_status)t->status;
 }
 
 tg_status tg_serve_release(tg_server* s, uint64_t ticket) {
