@@ -25,10 +25,10 @@
 //            counts by LDS atomics, ranking within each wave64 by ballot
 //            matching, digit offsets by a wave-level scan) on
 //            the depth bits alone, re-based to the segment's minimum (about
-//            three passes); runs of equal depth (frequent: a tile spans a
-//            narrow depth range) are then ordered by index, one lane per
-//            run, and only a run longer than 32 sends the tile to a sort on
-//            the composite (depth - min, index - min) key.
+//            three passes); runs of equal depth (Gaussians at exactly the
+//            same camera depth, rare in practice) are then ordered by index,
+//            one lane per run, and only a run longer than 32 sends the tile
+//            to a sort on the composite (depth - min, index - min) key.
 //            Either way the result is the unique (depth, index) order.
 //            Segments up to 2048 keys run in a 32 KB-LDS launch (four
 //            workgroups per CU), larger ones in a second launch with 128 KB
