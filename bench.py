@@ -342,6 +342,13 @@ def main():
                      "kernel": "k_render (tg_render_fwd)", "flops_per_launch": flops},
     }
     plain_fps = fps
+    # the paper's own figures, context only: its Gaussian count, latent width
+    # and feature-map size are not stated, so they are no baseline for this
+    # workload (rasterization time and end-to-end latency: Execution Time and
+    # System Latency, §5.3; frame rate: contributions, §1, and Table 1)
+    out["paper_context"] = {"rasterization_ms_per_system_frame": 1.0, "system_fps": 30,
+                            "end_to_end_latency_ms": 150, "hardware": "1x RTX 4090",
+                            "this_plain_frame_ms": round(ms_per_step, 4)}
     out["backward"] = bwd
     if not args.no_serve:
         srv = serve_leg(scene, g, args.streams, args.steps, args.warmup, torch)
