@@ -258,10 +258,13 @@ tg_status tg_serve_submit(tg_server* srv, const tg_request* req /* host */, uint
  * ticket stays readable until tg_serve_release. */
 tg_status tg_serve_poll(tg_server* srv, uint64_t ticket, tg_result* out);
 
-/* Blocks until the ticket is finished; returns its final status. */
+/* Blocks until the ticket is finished; returns its final status
+ * (TG_ERR_NOT_FOUND for an unknown ticket, or one that another caller
+ * releases while this one waits). */
 tg_status tg_serve_wait(tg_server* srv, uint64_t ticket, tg_result* out);
 
-/* Forget a finished ticket. */
+/* Forget a finished ticket (TG_PENDING, and nothing is forgotten, while it
+ * is queued or in flight). */
 tg_status tg_serve_release(tg_server* srv, uint64_t ticket);
 
 /* Stops the scheduler after the requests in flight finish (queued requests
