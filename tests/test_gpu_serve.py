@@ -180,6 +180,32 @@ def test_budget_and_capacity():
     srv.close()
 
 
+def test_wait_returns_when_another_caller_releases():
+    """Two callers wait on one ticket and one of them releases it: both
+    return (the other with the result or with TG_ERR_NOT_FOUND), none blocks."""
+    torch = torch_cuda()
+    from paper_2405_14866_amd import _native as N
+    from paper_2405_14866_amd.rasterize import GaussianSoA
+    from paper_2405_14866_amd.serve import Server
+    sc = _requests(1, seed=800)[0]
+    srv = Server(0, c=32, slots=1, max_batch=1, max_gauss_per_batch=60000, max_keys_per_batch=600000,
+                 max_pixels_per_batch=128 * 128, max_side=128)
+    g = GaussianSoA.from_scene(sc)
+    f = torch.empty((32, sc.cam.height, sc.cam.width), device="cuda")
+    torch.cuda.synchronize()
+    ticket = srv.submit(g, sc.cam, f)
+    other = []
+    th = threading.Thread(target=lambda: other.append(N.tg_serve_wait(srv.handle, ticket)[0]), daemon=True)
+    th.start()
+    res = srv.wait(ticket)                   # waits, then releases the ticket
+    th.join(timeout=30)
+    alive = th.is_alive()
+    if not alive:
+        srv.close()
+    assert not alive, "the second waiter did not return"
+    assert res.status == 0 and other[0] in (0, N.TG_ERR_NOT_FOUND), (res.status, other)
+
+
 def test_key_overflow_is_readmitted_alone():
     """A batch that overflows the slot's key capacity is re-admitted one
     request at a time; a request that overflows alone fails."""
