@@ -104,15 +104,9 @@ __device__ __forceinline__ Rect spec_f32(const CamArgs& c, float mx, float my, f
   return out;
 }
 
-__global__ void __launch_bounds__(256) k_project(BatchArgs a) {
-  const BatchHdr h = batch_hdr(a);
-  // clear the per-tile key counters that the binning accumulates into
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < h.n_tiles; t += gridDim.x * 256) a.tile_count[t] = 0;
-  const int64_t g0 = (int64_t)blockIdx.x * 256;       // 256-aligned: one request per workgroup
-  const int r = req_of_gauss(a, h, g0);
-  if (r < 0) return;
-  const ReqDev& q = batch_req(a, r);
-  const int64_t gi = g0 + threadIdx.x;
+// One Gaussian of request q (read through a reference whose address space
+// the caller fixes, so its fields are wave-uniform scalar loads).
+__device__ __forceinline__ void project_one(const BatchArgs& a, const ReqDev& q, int64_t gi) {
   const int64_t i = gi - q.g_off;
   const int64_t n = q.n;
   if (i >= n) return;
@@ -182,6 +176,18 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
   a.ext[gi] = ext;
   a.rect[gi] = rect;
   a.depth[gi] = rc.ok ? rc.key : 0xffffffffu;
+}
+
+__global__ void __launch_bounds__(256) k_project(BatchArgs a) {
+  const BatchHdr h = batch_hdr(a);
+  // clear the per-tile key counters that the binning accumulates into
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < h.n_tiles; t += gridDim.x * 256) a.tile_count[t] = 0;
+  const int64_t g0 = (int64_t)blockIdx.x * 256;       // 256-aligned: one request per workgroup
+  const int r = req_of_gauss(a, h, g0);
+  if (r < 0) return;
+  const int64_t gi = g0 + threadIdx.x;
+  if (a.table) project_one(a, a.table[r], gi);   // a batch's table in global memory
+  else project_one(a, a.one, gi);                // one request in the kernel arguments
 }
 
 }  // namespace

@@ -321,13 +321,9 @@ hipError_t launch_bwd_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s) {
 }
 
 // ------------------------------------------------------- project backward
-__global__ void __launch_bounds__(256) k_project_bwd(BatchArgs a) {
-  const BatchHdr h = batch_hdr(a);
-  const int64_t g0 = (int64_t)blockIdx.x * 256;
-  const int rq = req_of_gauss(a, h, g0);
-  if (rq < 0) return;
-  const ReqDev& qr = batch_req(a, rq);
-  const int64_t gi = g0 + threadIdx.x;
+// One Gaussian of request qr (read through a reference whose address
+// space the caller fixes, so its fields are wave-uniform scalar loads).
+__device__ __forceinline__ void project_bwd_one(const BatchArgs& a, const ReqDev& qr, int64_t gi) {
   const int64_t i = gi - qr.g_off;
   const int64_t n = qr.n;
   if (i >= n) return;
@@ -443,6 +439,16 @@ __global__ void __launch_bounds__(256) k_project_bwd(BatchArgs a) {
   if (qr.d_quat)
     for (int k = 0; k < 4; ++k) qr.d_quat[k * n + i] = (float)dq[k];
   if (qr.d_logit) qr.d_logit[i] = (float)dlg;
+}
+
+__global__ void __launch_bounds__(256) k_project_bwd(BatchArgs a) {
+  const BatchHdr h = batch_hdr(a);
+  const int64_t g0 = (int64_t)blockIdx.x * 256;
+  const int rq = req_of_gauss(a, h, g0);
+  if (rq < 0) return;
+  const int64_t gi = g0 + threadIdx.x;
+  if (a.table) project_bwd_one(a, a.table[rq], gi);   // a batch's table in global memory
+  else project_bwd_one(a, a.one, gi);                 // one request in the kernel arguments
 }
 
 }  // namespace
