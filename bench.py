@@ -195,6 +195,88 @@ def serve_leg(scene, g, streams, frames, warmup, torch, rate=240.0, open_frames=
                           "mean_batch": round(sum(obatch) / len(obatch), 2)}}
 
 
+def mixed_serving_leg(torch, streams=8, requests=2000, rate=240.0, closed=400):
+    """The serving workload itself: stream s keeps one Gaussian set resident
+    (N ~ U{100k..1M} from the small-scene generator, C = 32); request k comes
+    from stream k mod `streams` with its own target (512^2 / 768^2 / 1024^2,
+    yaw +-10 deg, pitch +-5 deg).  Open loop: `requests` Poisson arrivals at
+    `rate` per second, latency submit -> observed completion.  Closed loop:
+    two requests in flight per stream until `closed` complete."""
+    import numpy as np
+    import scenes
+    from paper_2405_14866_amd.rasterize import GaussianSoA
+    from paper_2405_14866_amd.serve import Server
+    scs = [scenes.make_cfg4_request(i) for i in range(streams)]
+    gs = [GaussianSoA.from_scene(sc) for sc in scs]
+    c = 32
+    side = 1024
+    bufs = [[torch.empty(c * side * side, device="cuda") for _ in range(2)] for _ in range(streams)]
+    abufs = [[torch.empty(side * side, device="cuda") for _ in range(2)] for _ in range(streams)]
+    cams = [scenes.serving_camera(k) for k in range(max(requests, closed))]
+    n_max = max(sc.n for sc in scs)
+    batch = 8
+    srv = Server(0, c=c, slots=3, max_batch=batch, max_gauss_per_batch=batch * n_max + 8192,
+                 max_keys_per_batch=int(batch * n_max * 4.5), max_pixels_per_batch=batch * side * side,
+                 max_side=side, use_graph=True, keys_per_gaussian=4.5)
+
+    def submit(k, slot):
+        i = k % streams
+        cam = cams[k]
+        h, w = cam.height, cam.width
+        f = bufs[i][slot][:c * h * w].view(c, h, w)
+        a = abufs[i][slot][:h * w].view(h, w)
+        return srv.submit(gs[i], cam, f, a, stream_id=i)
+
+    for k in range(2 * streams):                        # warm-up
+        srv.wait(submit(k, 0))
+    torch.cuda.synchronize()
+    # closed loop
+    t0 = time.perf_counter()
+    inflight, submitted, done, clat = [], 0, 0, []
+    for k in range(min(2 * streams, closed)):
+        inflight.append(submit(k, k // streams))
+        submitted += 1
+    while inflight:
+        t = inflight.pop(0)
+        r = srv.wait(t)
+        assert r.status == 0, r.status
+        clat.append(r.latency_ms)
+        done += 1
+        if submitted < closed:
+            inflight.append(submit(submitted, (submitted // streams) % 2))
+            submitted += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # open loop
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, requests))
+    pending, olat, obatch = [], [], []
+    t1 = time.perf_counter()
+    for k, ta in enumerate(arrivals):
+        while time.perf_counter() - t1 < ta:
+            if pending and srv.poll(pending[0]).status != 1:
+                r = srv.wait(pending.pop(0))
+                assert r.status == 0, r.status
+                olat.append(r.latency_ms)
+                obatch.append(r.batch_size)
+            else:
+                time.sleep(20e-6)
+        # a stream's two output buffers alternate; its previous request on a
+        # buffer has long finished at 30 requests/s per stream
+        pending.append(submit(k, (k // streams) % 2))
+    for t in pending:
+        r = srv.wait(t)
+        assert r.status == 0, r.status
+        olat.append(r.latency_ms)
+        obatch.append(r.batch_size)
+    srv.close()
+    pct = lambda xs, q: float(np.percentile(xs, q))
+    return {"requests": len(olat), "rate_per_s": rate, "p50_ms": round(pct(olat, 50), 4),
+            "p99_ms": round(pct(olat, 99), 4), "mean_batch": round(float(np.mean(obatch)), 2),
+            "closed_loop_frames_per_s": round(done / wall, 2), "closed_loop_requests": done,
+            "n_per_stream": [sc.n for sc in scs], "streams": streams}
+
+
 def backward_leg(fr, gs, scene, s, steps, warmup, fwd_step, torch):
     """tg_render_bwd on the realistic frame (blend adjoint + projection
     adjoint) and a whole training step (forward path + adjoint), per-call
@@ -361,6 +443,8 @@ def main():
         out["p50_ms"], out["p99_ms"] = srv["open_loop"]["p50_ms"], srv["open_loop"]["p99_ms"]
         out["gaussians_per_s"] = round(n * srv["frames_per_s"], 1)
         out["vs_plain"] = round(srv["frames_per_s"] / plain_fps, 3)
+        # the serving workload with its own request mix (uneven N, resolutions, poses)
+        out["serving_mixed"] = mixed_serving_leg(torch)
         out["hbm"]["GBps"] = round(alg_bytes * srv["frames_per_s"] / 1e9, 1)
         out["hbm"]["frac_of_peak"] = round(alg_bytes * srv["frames_per_s"] / 1e9 / HBM_PEAK_GBPS, 4)
         out["config"]["workload"] = out["config"]["workload"].replace(

@@ -281,6 +281,18 @@ def make_cfg4_request(req_id: int, base_seed: int = 40000):
     return sc
 
 
+def serving_camera(req_id: int, base_seed: int = 41000) -> Camera:
+    """Target camera of one serving request: resolution drawn from {512, 768,
+    1024} (focal length equal to the resolution, as in make_cfg4_request),
+    pose jittered +-10 deg yaw / +-5 deg pitch about frontal."""
+    rng = np.random.default_rng(base_seed + req_id)
+    res = int(rng.choice([512, 768, 1024]))
+    yaw = float(rng.uniform(-10.0, 10.0))
+    pitch = float(rng.uniform(-5.0, 5.0))
+    return orbit_camera(yaw, pitch, (0.0, 0.0, 1.5), 1.5, float(res), float(res), res / 2.0, res / 2.0,
+                        res, res)
+
+
 def make_cfg5(seed: int = 50, frame: int = 0, base: Scene | None = None) -> Scene:
     """Full-resolution stress: 4 views of 2048x2048 (about 7.5M Gaussians),
     C = 32, 2048x2048 target.  Frame k perturbs the features by N(0, 0.05)."""
