@@ -59,3 +59,42 @@ def test_product_does_not_reach_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.lower(), f
                 assert "tgo_" not in txt and "libtgo" not in txt, f
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it says so and exits with
+    status 2 before touching a device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2, (p.returncode, p.stderr[-500:])
+    line = json.loads(p.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_serving_cameras_follow_the_request_recipe():
+    """Serving request targets: resolution in {512, 768, 1024} with the focal
+    length equal to it, principal point at the centre, the camera 1.5 m from
+    the pivot (0, 0, 1.5), yaw within +-10 deg and pitch within +-5 deg, and
+    the same request id gives the same camera."""
+    import numpy as np
+    import scenes
+    res = set()
+    for k in range(60):
+        cam = scenes.serving_camera(k)
+        assert cam.width == cam.height and cam.width in (512, 768, 1024)
+        assert cam.fx == cam.fy == cam.width and cam.cx == cam.cy == cam.width / 2
+        R, t = np.asarray(cam.R, np.float64), np.asarray(cam.t, np.float64)
+        centre = -R.T @ t                           # camera centre in world coordinates
+        d = centre - np.array([0.0, 0.0, 1.5])
+        assert abs(np.linalg.norm(d) - 1.5) < 1e-5
+        yaw = np.degrees(np.arctan2(-d[0], -d[2]))
+        pitch = np.degrees(np.arcsin(np.clip(d[1] / 1.5, -1, 1)))
+        assert abs(yaw) <= 10.0 + 1e-4 and abs(pitch) <= 5.0 + 1e-4, (yaw, pitch)
+        res.add(cam.width)
+    assert res == {512, 768, 1024}
+    a, b = scenes.serving_camera(7), scenes.serving_camera(7)
+    assert np.array_equal(a.R, b.R) and np.array_equal(a.t, b.t) and a.width == b.width
