@@ -122,8 +122,8 @@ tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max
                           int64_t max_keys, tg_frame** out);
 void tg_frame_destroy(tg_frame* frame);
 
-/* Step 1 -- projection (§4.2 "rasterized to the targeted novel views given
- * their projection matrix Pi_novel").  Per Gaussian: camera transform,
+/* Step 1 -- projection (§4.2: the Gaussians are splatted into each target
+ * view through its projection Pi_novel).  Per Gaussian: camera transform,
  * EWA 2D covariance with dilation, conic, 3-sigma radius, tile rectangle,
  * depth key, cull.  Reads g (n <= max_n), writes the frame's 2D state.
  * cam is a host pointer; its width/height must fit the frame. */
@@ -131,7 +131,12 @@ tg_status tg_project(tg_frame* frame, const tg_gaussians* g, const tg_camera* ca
 
 /* Step 2 -- binning: count (tile, Gaussian) keys per tile, scan, scatter the
  * keys into per-tile segments and sort each segment by (depth key, index)
- * with an LDS radix sort.  Uses the state of the last tg_project. */
+ * with an LDS radix sort.  Uses the state of the last tg_project.
+ * The paper is silent on binning: §4.2 cites the tile-based 3D Gaussian
+ * splatting rasterizer, whose front-to-back blend needs each 16x16 tile's
+ * Gaussians in depth order; this call produces exactly that order, with the
+ * Gaussian index breaking depth ties.  Errors: TG_ERR_INVALID for a null
+ * frame or one never projected; key overflow is reported by tg_frame_check. */
 tg_status tg_bin_sort(tg_frame* frame, void* stream);
 
 /* Step 3 -- front-to-back blend (F_novel of §4.2).  out_feat [c][H][W]

@@ -667,8 +667,9 @@ int tgo_pixel_variants(void* h, int px, int py, const double* bg, double* out) {
     BlendOpts op;
     op.flip = &flip;
     blend_pixel(k, k.proj.data(), k.list.data() + s, len, px + 0.5, py + 0.5, F.data(), run, op);
-    for (int ch = 0; ch < C; ++ch) out[nv * (C + 1) + ch] = F[ch] + run.T * (bg ? bg[ch] : 0.0);
-    out[nv * (C + 1) + C] = 1.0 - run.T;
+    for (int ch = 0; ch < C; ++ch)
+      out[nv * (C + 1) + ch] = F[ch] + PLANT(11, run.T * (bg ? bg[ch] : 0.0), 0.0);
+    out[nv * (C + 1) + C] = PLANT(10, 1.0 - run.T, run.T);
     ++nv;
   }
   return nv;

@@ -146,10 +146,12 @@ def test_run_twice_is_bitwise_identical(cfg1):
 
 
 def test_long_tile_segment_uses_global_sort():
-    """More keys in one tile than the LDS sort holds (4096): the segment is
-    sorted in global memory with the same passes; lists stay bit-exact."""
+    """More keys in one tile than the 128 KB LDS sort holds (8192): 12,000
+    tiny Gaussians inside tile (0, 0) (radius 2 px around centres in
+    [2, 14] px), so that segment is sorted on the global scratch buffers with
+    the composite (depth, index) passes; lists stay bit-exact."""
     rng = np.random.default_rng(9)
-    n = 6000
+    n = 12000
     z = rng.uniform(1.0, 3.0, n)
     u = rng.uniform(2, 14, n); v = rng.uniform(2, 14, n)
     means = np.stack([(u - 32) * z / 64, (v - 32) * z / 64, z])
@@ -157,7 +159,34 @@ def test_long_tile_segment_uses_global_sort():
                                       feat=rng.standard_normal((n, 8)), cam=_cam())
     gpu, _, _ = gpu_render(sc)
     ora = oracle.Oracle(sc)
-    assert np.diff(gpu["tile_start"]).max() > 4096
+    counts = np.diff(gpu["tile_start"])
+    assert counts[0] == n and counts.max() > 8192
+    compare_lists(gpu, ora)
+    compare_forward(gpu, ora)
+
+
+@pytest.mark.parametrize("n_tie,n_other", [(100, 300), (50, 3000)])
+def test_equal_depth_runs_take_the_composite_sort(n_tie, n_other):
+    """A run of more than 32 keys with bit-identical float32 depth in one tile
+    (Gaussians on the fronto-parallel plane z = 1.5 under the identity camera,
+    so t_z = z exactly) sends the tile to the sort on the composite
+    (depth, index) key; with 400 keys that is the 32 KB-LDS launch, with 3,050
+    the 128 KB one.  The run is interleaved in index order with Gaussians at
+    other depths; lists stay bit-exact (ties in index order)."""
+    rng = np.random.default_rng(100 + n_tie)
+    n = n_tie + n_other
+    z = rng.uniform(1.0, 2.0, n)
+    tie = rng.choice(n, n_tie, replace=False)
+    z[tie] = 1.5
+    u = rng.uniform(3, 13, n); v = rng.uniform(3, 13, n)
+    means = np.stack([(u - 32) * z / 64, (v - 32) * z / 64, z])
+    sc = scenes.single_gaussian_scene(means, 0.002, opacity=rng.uniform(0.05, 0.5, n),
+                                      feat=rng.standard_normal((n, 8)), cam=_cam())
+    ora = oracle.Oracle(sc)
+    _, key, _ = ora.spec()
+    assert (key == np.float32(1.5).view(np.uint32)).sum() == n_tie
+    gpu, _, _ = gpu_render(sc)
+    assert np.diff(gpu["tile_start"])[0] == n
     compare_lists(gpu, ora)
     compare_forward(gpu, ora)
 

@@ -24,6 +24,8 @@ MUTANTS = {
     7: "2-sigma instead of 3-sigma rectangle",
     8: "tile lists ignore depth order",
     9: "mean gradient uses W instead of W^T",
+    10: "branch variants report T in the alpha column",
+    11: "branch variants drop the T bg term",
 }
 
 

@@ -366,3 +366,78 @@ def test_backward_under_a_chosen_branch(cfg1):
             for k in ("g2d", "feat", "mean", "quat"):
                 assert np.array_equal(g[k], plain[k]), k
     assert np.abs(feats[1] - feats[0]).max() > 1e-6
+
+
+# ------------------------------------------------- near-threshold branch variants
+def _iso_alpha(mean, s, o, px, py, fx=64.0, cx=32.0, clamp=True):
+    """Closed-form alpha of an isotropic Gaussian (identity camera) at pixel
+    centre (px + 0.5, py + 0.5), from the float32-rounded inputs: Sigma2D =
+    s^2 J J^T with the full perspective Jacobian, 0.3 px^2 on the diagonal,
+    alpha = min(0.99, o exp(-d^T Sigma'^-1 d / 2)) (o G without the clamp
+    when clamp is False)."""
+    X, Y, Z = (_f32(v) for v in mean)
+    s, o = _f32(s), _f32(o)
+    J = np.array([[fx / Z, 0, -fx * X / Z ** 2], [0, fx / Z, -fx * Y / Z ** 2]])
+    S2 = s * s * J @ J.T + 0.3 * np.eye(2)
+    d = np.array([px + 0.5 - (fx * X / Z + cx), py + 0.5 - (fx * Y / Z + cx)])
+    a = o * math.exp(-0.5 * d @ np.linalg.solve(S2, d))
+    return min(0.99, a) if clamp else a
+
+
+@pytest.mark.parametrize("delta", [3e-5, -3e-5])
+def test_variants_alpha_band_closed_form(delta):
+    """One Gaussian whose alpha at pixel (35, 31) is 1/255 (1 + delta), inside
+    the band where an FP32 renderer may skip or blend it, on a non-black
+    background.  The two variants are, in the plain walk's order first, the
+    closed forms skip = (bg, 0) and blend = (alpha f + (1 - alpha) bg, alpha)."""
+    mean, s = (0.0, 0.0, 1.5), 0.03
+    g1 = _iso_alpha(mean, s, 1.0, 35, 31, clamp=False)    # the Gaussian factor at the pixel
+    o = (1.0 / 255.0) * (1.0 + delta) / g1
+    a = _iso_alpha(mean, s, o, 35, 31)
+    assert abs(a * 255.0 - 1.0) < 5e-5 and (a >= 1 / 255) == (delta > 0)
+    f = np.array([1.0, -2.0, 0.5])
+    bg = np.array([0.3, -0.7, 0.2])
+    sc = scenes.single_gaussian_scene(mean, s, opacity=o, feat=[f], cam=_cam())
+    ora = oracle.Oracle(sc)
+    assert ora.render(bg=bg)["nflags"][31, 35] == 1
+    var = ora.pixel_variants(35, 31, bg=bg)
+    skip = np.concatenate([bg, [0.0]])
+    blend = np.concatenate([a * f + (1.0 - a) * bg, [a]])
+    want = [blend, skip] if delta > 0 else [skip, blend]
+    assert var.shape == (2, 4)
+    np.testing.assert_allclose(var, np.array(want), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("delta", [5e-5, -5e-5])
+def test_variants_transmittance_band_closed_form(delta):
+    """Three Gaussians stacked on the centre of pixel (32, 32) at depths 1.2,
+    1.4, 1.6 with alphas 0.95, 0.95 and a third chosen so that the
+    transmittance after it is 1e-4 (1 + delta), inside the band where an FP32
+    renderer may stop before it or blend it, on a non-black background.  The
+    variants are the closed forms: blend all three, (sum w_i f_i + T3 bg,
+    1 - T3), and stop before the third, (w1 f1 + w2 f2 + T2 bg, 1 - T2)."""
+    depths = (1.2, 1.4, 1.6)
+    means = [(0.5 * z / 64, 0.5 * z / 64, z) for z in depths]
+    s = 0.01
+    G = [_iso_alpha(m, s, 1.0, 32, 32, clamp=False) for m in means]
+    o12 = [_f32(0.95 / G[0]), _f32(0.95 / G[1])]
+    a1, a2 = (_iso_alpha(means[k], s, o12[k], 32, 32) for k in range(2))
+    T1 = 1.0 - a1
+    T2 = T1 * (1.0 - a2)
+    o3 = _f32((1.0 - 1e-4 * (1.0 + delta) / T2) / G[2])
+    a3 = _iso_alpha(means[2], s, o3, 32, 32)
+    T3 = T2 * (1.0 - a3)
+    assert abs(T3 / 1e-4 - 1.0) < 3e-4 and (T3 >= 1e-4) == (delta > 0)
+    f = np.array([[1.0, 0.5], [10.0, -1.0], [100.0, 2.0]])
+    bg = np.array([0.25, -0.5])
+    sc = scenes.single_gaussian_scene(np.array(means).T, s, opacity=[o12[0], o12[1], o3], feat=f,
+                                      cam=_cam())
+    ora = oracle.Oracle(sc)
+    assert ora.render(bg=bg)["nflags"][32, 32] == 1
+    var = ora.pixel_variants(32, 32, bg=bg)
+    w = [a1, a2 * T1, a3 * T2]
+    blend = np.concatenate([w[0] * f[0] + w[1] * f[1] + w[2] * f[2] + T3 * bg, [1.0 - T3]])
+    stop = np.concatenate([w[0] * f[0] + w[1] * f[1] + T2 * bg, [1.0 - T2]])
+    want = [blend, stop] if delta > 0 else [stop, blend]
+    assert var.shape == (2, 3)
+    np.testing.assert_allclose(var, np.array(want), rtol=0, atol=1e-12)
