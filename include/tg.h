@@ -191,6 +191,32 @@ tg_status tg_frame_lists(tg_frame* frame, int32_t* tile_start, int32_t* sorted, 
  * -1 if none).  Either output may be NULL. */
 tg_status tg_frame_pixel_state(tg_frame* frame, float* T_final, int32_t* last, void* stream);
 
+/* ------------------------------------------- render without allocating
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * render as tg_project + tg_bin_sort + tg_render_fwd on a frame (same
+ * kernels, bit-identical results), with the workspace in a static device
+ * array of TG_NOALLOC_SCRATCH_BYTES (86 MiB) instead of a tg_frame: no call
+ * to hipMalloc, hipFree or any allocating routine.  Each device holds its
+ * own array for the life of the process; tg_ctx_create resolves its address
+ * on the context's device.  Limits: g->n <= TG_NOALLOC_MAX_N, width x height
+ * <= TG_NOALLOC_MAX_PIXELS, ceil(W/16) x ceil(H/16) <= TG_NOALLOC_MAX_TILES
+ * (TG_ERR_CAPACITY before anything is enqueued otherwise), and at most
+ * TG_NOALLOC_MAX_KEYS (tile, Gaussian) keys: with more, the binning marks
+ * the render, the outputs are not written and *status (a device int32,
+ * optional) receives TG_ERR_CAPACITY, else TG_OK, once the stream reaches
+ * that point.  Every call on a device shares that device's array: calls
+ * that overlap on one device (two streams, two threads) race and must be
+ * serialised by the caller.  Arguments as for tg_render_fwd; cam (host) as
+ * for tg_project. */
+#define TG_NOALLOC_MAX_N 524288
+#define TG_NOALLOC_MAX_KEYS 2097152
+#define TG_NOALLOC_MAX_PIXELS 1048576
+#define TG_NOALLOC_MAX_TILES 8192
+#define TG_NOALLOC_SCRATCH_BYTES 90309120
+tg_status tg_render_noalloc(tg_ctx* ctx, const tg_gaussians* g, const tg_camera* cam, const float* bg,
+                            float* out_feat, float* out_alpha, int32_t* status, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request loop that renders many target views at once (the system of §5.3
  * renders every frame of every terminal through R_G, under CUDA Graphs).

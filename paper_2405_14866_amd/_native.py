@@ -30,7 +30,14 @@ EXPORTS = [
     "tg_frame_check", "tg_frame_lists", "tg_frame_pixel_state", "tg_render_fwd_counted",
     "tg_frame_work", "tg_serve_create", "tg_serve_stream_arena", "tg_serve_submit",
     "tg_serve_poll", "tg_serve_wait", "tg_serve_release", "tg_serve_destroy",
+    "tg_render_noalloc",
 ]
+
+# limits of tg_render_noalloc (include/tg.h)
+TG_NOALLOC_MAX_N = 524288
+TG_NOALLOC_MAX_KEYS = 2097152
+TG_NOALLOC_MAX_PIXELS = 1048576
+TG_NOALLOC_MAX_TILES = 8192
 
 
 class tg_camera(ct.Structure):
@@ -128,6 +135,8 @@ def lib():
     L.tg_frame_lists.argtypes = [P, P, P, I64, P]
     L.tg_frame_pixel_state.restype = I
     L.tg_frame_pixel_state.argtypes = [P, P, P, P]
+    L.tg_render_noalloc.restype = I
+    L.tg_render_noalloc.argtypes = [P, ct.POINTER(tg_gaussians), ct.POINTER(tg_camera), P, P, P, P, P]
     _lib = L
     return L
 
@@ -206,6 +215,12 @@ def tg_frame_lists(frame: int, tile_start: int, sorted_: int, n_keys: int, strea
 
 def tg_frame_pixel_state(frame: int, T_final: int, last: int, stream: int) -> int:
     return lib().tg_frame_pixel_state(frame, T_final, last, stream)
+
+
+def tg_render_noalloc(ctx: int, g: tg_gaussians, cam: tg_camera, bg: int, out_feat: int,
+                      out_alpha: int, status: int, stream: int) -> int:
+    return lib().tg_render_noalloc(ctx, ct.byref(g), ct.byref(cam), bg, out_feat, out_alpha, status,
+                                   stream)
 
 
 def tg_serve_create(ctx: int, opts: tg_serve_opts) -> int:

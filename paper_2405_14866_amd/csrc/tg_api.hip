@@ -50,6 +50,7 @@ struct tg_frame {
 
 namespace tg {
 int ctx_device(const tg_ctx* c) { return c->device; }
+hipError_t noalloc_setup(int device);   // noalloc.hip
 }  // namespace tg
 
 namespace {
@@ -150,6 +151,8 @@ tg_status tg_ctx_create(int device, tg_ctx** out) {
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TG_ERR_INVALID;
   DeviceGuard guard(device);
   if (tg::bin_set_attributes() != hipSuccess) return TG_ERR_HIP;
+  // the static workspace of tg_render_noalloc: its address on this device
+  if (tg::noalloc_setup(device) != hipSuccess) return TG_ERR_HIP;
   tg_ctx* c = new (std::nothrow) tg_ctx;
   if (!c) return TG_ERR_OOM;
   c->device = device;
