@@ -242,12 +242,25 @@ typedef struct tg_serve_opts {
   int32_t batch_window_us;      /* a free slot waits up to this long after the oldest queued
                                    request arrived for more requests before it launches a
                                    batch of fewer than max_batch (0: launch at once), 0..1e6 */
+  int32_t backward;             /* 1: slots also hold the adjoint's workspace and accept
+                                   requests that carry an upstream gradient */
 } tg_serve_opts;
 
 /* One render request.  g points at device buffers that the caller keeps
  * resident (for instance the stream's arena from tg_serve_stream_arena) and
  * must not modify until the request is done; out_feat [c][H][W] and
- * out_alpha [H][W] (or NULL) are device buffers the caller owns. */
+ * out_alpha [H][W] (or NULL) are device buffers the caller owns.
+ * Differentiation (§4.2 trains through R_G; a server created with backward
+ * = 1): with d_feat [c][H][W] (and d_alpha [H][W] or NULL) the request also
+ * runs the adjoint of its render in the same batch and writes the raw-
+ * parameter gradients of tg_render_bwd into grads (d_feat required unless
+ * g.n == 0, the others may be NULL); d_feat NULL renders only.
+ * share = 1 lets the request reuse the projection and sorted tile lists of
+ * an earlier request of the same batch and stream_id with the same n and
+ * an identical camera (consecutive frames whose geometry did not change,
+ * only their features).  The reuse is checked on the device: if any byte of
+ * the two requests' mean, scale, quat or opacity differs, the request is
+ * rendered again on its own (counted in tg_result.retries). */
 typedef struct tg_request {
   int32_t stream_id;
   tg_gaussians g;
@@ -255,13 +268,19 @@ typedef struct tg_request {
   const float* bg;              /* [c] or NULL */
   float* out_feat;
   float* out_alpha;
+  const float* d_feat;          /* upstream gradient dL/dF or NULL */
+  const float* d_alpha;         /* upstream gradient dL/dalpha or NULL */
+  tg_grads grads;
+  int32_t share;
 } tg_request;
 
 typedef struct tg_result {
   int32_t status;               /* TG_OK, TG_PENDING or an error code */
   int32_t batch_size;           /* requests in the batch that rendered it */
   int32_t slot;
-  int32_t retries;              /* re-admissions after a key-capacity overflow */
+  int32_t retries;              /* re-admissions (key-capacity overflow, geometry not shared) */
+  int32_t shared;               /* 1: rendered with the projection and lists of an earlier request */
+  int32_t pad;
   int64_t t_submit_ns;          /* host steady clock, nanoseconds */
   int64_t t_launch_ns;
   int64_t t_done_ns;            /* when the server observed completion */

@@ -63,18 +63,20 @@ class tg_serve_opts(ct.Structure):
                 ("max_gauss_per_batch", ct.c_int64), ("max_keys_per_batch", ct.c_int64),
                 ("max_pixels_per_batch", ct.c_int64), ("max_side", ct.c_int32), ("c", ct.c_int32),
                 ("use_graph", ct.c_int32), ("keys_per_gaussian", ct.c_float),
-                ("batch_window_us", ct.c_int32)]
+                ("batch_window_us", ct.c_int32), ("backward", ct.c_int32)]
 
 
 class tg_request(ct.Structure):
     _fields_ = [("stream_id", ct.c_int32), ("g", tg_gaussians), ("cam", tg_camera),
-                ("bg", ct.c_void_p), ("out_feat", ct.c_void_p), ("out_alpha", ct.c_void_p)]
+                ("bg", ct.c_void_p), ("out_feat", ct.c_void_p), ("out_alpha", ct.c_void_p),
+                ("d_feat", ct.c_void_p), ("d_alpha", ct.c_void_p), ("grads", tg_grads),
+                ("share", ct.c_int32)]
 
 
 class tg_result(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("batch_size", ct.c_int32), ("slot", ct.c_int32),
-                ("retries", ct.c_int32), ("t_submit_ns", ct.c_int64), ("t_launch_ns", ct.c_int64),
-                ("t_done_ns", ct.c_int64)]
+                ("retries", ct.c_int32), ("shared", ct.c_int32), ("pad", ct.c_int32),
+                ("t_submit_ns", ct.c_int64), ("t_launch_ns", ct.c_int64), ("t_done_ns", ct.c_int64)]
 
 
 class TgError(RuntimeError):

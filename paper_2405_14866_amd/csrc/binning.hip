@@ -60,6 +60,7 @@ __device__ __forceinline__ bool chunk_req(const BatchArgs& a, const BatchHdr& h,
   c.r = req_of_gauss(a, h, g0);
   if (c.r < 0) return false;
   const ReqDev& q = batch_req(a, c.r);
+  if (q.src != 0) return false;       // a sharing request bins nothing of its own
   c.g_off = q.g_off;
   c.i0 = g0 - q.g_off;
   c.i1 = min(q.n, c.i0 + BIN_CHUNK);
@@ -99,6 +100,37 @@ __global__ void __launch_bounds__(1024) k_count(BatchArgs a) {
       const int v = bins[t];
       if (v) atomicAdd(&gcount[t], v);
     }
+  }
+}
+
+// Tiles of a request that shares an earlier request's projection take that
+// request's key counts (so the scan reserves their segments and orders
+// them by length like any other tile).
+__global__ void __launch_bounds__(256) k_share_count(BatchArgs a) {
+  const BatchHdr h = batch_hdr(a);
+  if (h.n_shared == 0) return;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < h.n_tiles; t += gridDim.x * 256) {
+    const int r = req_of_tile(a, h, t);
+    if (r < 0) continue;
+    const ReqDev& q = batch_req(a, r);
+    if (q.src == 0) continue;
+    a.tile_count[t] = a.tile_count[batch_req(a, q.src - 1).tile_off + (t - q.tile_off)];
+  }
+}
+
+// ... and, once the source's segments are sorted, copies of them.
+__global__ void __launch_bounds__(256) k_share_copy(BatchArgs a) {
+  if (a.dev->overflow) return;
+  const BatchHdr h = batch_hdr(a);
+  if (h.n_shared == 0) return;
+  for (int t = blockIdx.x; t < h.n_tiles; t += gridDim.x) {
+    const int r = req_of_tile(a, h, t);
+    if (r < 0) continue;
+    const ReqDev& q = batch_req(a, r);
+    if (q.src == 0) continue;
+    const int ts = batch_req(a, q.src - 1).tile_off + (t - q.tile_off);
+    const int d = a.tile_start[t], n = a.tile_start[t + 1] - d, sidx = a.tile_start[ts];
+    for (int j = threadIdx.x; j < n; j += 256) a.sorted[d + j] = a.sorted[sidx + j];
   }
 }
 
@@ -446,7 +478,8 @@ __global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
   __shared__ uint64_t bufA[CAP];
   __shared__ uint64_t bufB[CAP];
   __shared__ SortShared sh;
-  const int nt = batch_hdr(a).n_tiles;
+  const BatchHdr h = batch_hdr(a);
+  const int nt = h.n_tiles;
   for (int i = blockIdx.x; i < nt; i += gridDim.x) {
     const int t = a.tile_order[i];
     const int s = a.tile_start[t];
@@ -456,6 +489,7 @@ __global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
       continue;
     }
     if (n > hi) continue;
+    if (h.n_shared > 0 && batch_req(a, req_of_tile(a, h, t)).src != 0) continue;   // copied later
     sort_tile<CAP>(a, s, n, bufA, bufB, sh);
     __syncthreads();                 // LDS is reused by the next tile
   }
@@ -472,9 +506,15 @@ hipError_t launch_bin_sort(const BatchArgs& a, int64_t grid_gauss, int32_t grid_
   const int grid = (int)(chunks > 0 ? chunks : 1);
   const size_t shm = (size_t)min(max_tiles_per_req, BIN_LDS_MAX_TILES) * sizeof(int32_t);
   const int gt = grid_tiles > 0 ? grid_tiles : 1;
+  const bool sharing = a.table != nullptr;    // only a replayed batch can hold sharing requests
+  const int share_grid = gt < 1024 ? gt : 1024;
   hipLaunchKernelGGL(k_count, dim3(grid), dim3(1024), shm, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  if (sharing) {
+    hipLaunchKernelGGL(k_share_count, dim3((gt + 255) / 256 < 1024 ? (gt + 255) / 256 : 1024), dim3(256), 0, s, a);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(k_fill, dim3(grid), dim3(1024), shm, s, a);
@@ -483,7 +523,12 @@ hipError_t launch_bin_sort(const BatchArgs& a, int64_t grid_gauss, int32_t grid_
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL((k_sort<SORT_LARGE, true>), dim3(gt < 256 ? gt : 256), dim3(256), 0, s, a, SORT_SMALL,
                      0x7fffffff);
-  return hipGetLastError();
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (sharing) {
+    hipLaunchKernelGGL(k_share_copy, dim3(share_grid), dim3(256), 0, s, a);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 hipError_t bin_set_attributes() {

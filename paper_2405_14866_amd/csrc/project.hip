@@ -186,8 +186,11 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
   const int r = req_of_gauss(a, h, g0);
   if (r < 0) return;
   const int64_t gi = g0 + threadIdx.x;
-  if (a.table) project_one(a, a.table[r], gi);   // a batch's table in global memory
-  else project_one(a, a.one, gi);                // one request in the kernel arguments
+  if (a.table) {                                 // a batch's table in global memory
+    if (a.table[r].src == 0) project_one(a, a.table[r], gi);   // a sharing request reads its source's state
+  } else {
+    project_one(a, a.one, gi);                   // one request in the kernel arguments
+  }
 }
 
 }  // namespace

@@ -145,7 +145,8 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
   const int tmax = sh.smax;
 
   float* const d_feat = q.d_feat;
-  const int64_t g_off = q.g_off;
+  const int64_t g_off = q.s_off;              // the list holds indices of this 2D-state range
+  const int64_t acc_off = q.g_off - q.s_off;  // ... the adjoint accumulates in the request's own range
   for (int b = tmax >= 0 ? tmax / BWD_B : -1; b >= 0; --b) {
     const int b0 = b * BWD_B;
     const int nb = min(BWD_B, tmax + 1 - b0);
@@ -256,7 +257,7 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
         const float sdxx = mxx - 2.f * u * mx + u * u * m1;
         const float sdxy = mxy - u * my - v * mx + u * v * m1;
         const float sdyy = myy - 2.f * v * my + v * v * m1;
-        float* g2 = a.g2d + gi;
+        float* g2 = a.g2d + (gi + acc_off);
         const int64_t gc = a.g_cap;
         atomic_add_global(g2, cn.x * sdx + cn.y * sdy);
         atomic_add_global(g2 + gc, cn.z * sdy + cn.y * sdx);
@@ -290,6 +291,7 @@ __global__ void __launch_bounds__(256) k_render_bwd(BatchArgs a) {
     const int r = req_of_tile(a, h, t);
     if (r < 0) break;
     const ReqDev& q = batch_req(a, r);
+    if (!q.d_img) continue;          // a forward-only request of a mixed batch
     const int lt = t - q.tile_off;
     bwd_tile<C>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, sh);
   }
@@ -299,14 +301,17 @@ __global__ void __launch_bounds__(256) k_render_bwd(BatchArgs a) {
   }
 }
 
-// zero the 2D accumulators of the batch and each request's feature gradient
+// zero the 2D accumulators of the batch's index range and the feature
+// gradient of each request that asks for an adjoint
 __global__ void k_bwd_zero(BatchArgs a, int c) {
   const BatchHdr h = batch_hdr(a);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = i0; i < 6 * a.g_cap; i += stride) a.g2d[i] = 0.f;
+  for (int k = 0; k < 6; ++k)
+    for (int64_t i = i0; i < h.g_end; i += stride) a.g2d[k * a.g_cap + i] = 0.f;
   for (int r = 0; r < h.n_req; ++r) {
     const ReqDev& q = batch_req(a, r);
+    if (!q.d_img || !q.d_feat) continue;
     for (int64_t i = i0; i < q.n * c; i += stride) q.d_feat[i] = 0.f;
   }
 }
@@ -326,10 +331,10 @@ hipError_t launch_bwd_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s) {
 __device__ __forceinline__ void project_bwd_one(const BatchArgs& a, const ReqDev& qr, int64_t gi) {
   const int64_t i = gi - qr.g_off;
   const int64_t n = qr.n;
-  if (i >= n) return;
+  if (i >= n || !qr.d_img) return;            // no adjoint asked for this request
   const int64_t gc = a.g_cap;
   double dmu[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dlg = 0;
-  const uint2 r = a.rect[gi];
+  const uint2 r = a.rect[qr.s_off + i];       // the projection this request's render used
   const bool live = (r.x & 0xffffu) <= (r.x >> 16);
   if (live) {
     const CamArgs& c = qr.cam;

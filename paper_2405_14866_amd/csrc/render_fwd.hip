@@ -153,7 +153,7 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   const int len = e - s;
   const uint32_t qbit = 1u << w;
   const float* feat = q.feat;
-  const int64_t g_off = q.g_off;
+  const int64_t g_off = q.s_off;      // the list holds indices of this 2D-state range
 
   constexpr int NM = C / 4;           // MFMA updates per blend step
   const int q4 = lane & 3;

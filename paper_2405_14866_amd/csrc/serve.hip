@@ -19,12 +19,22 @@
 //   * slots run on separate streams, so a batch formed while others are on
 //     the GPU overlaps with them on the device;
 //   * a batch whose keys overflow the slot is re-admitted request by request
-//     (a request that overflows alone fails with TG_ERR_CAPACITY).
+//     (a request that overflows alone fails with TG_ERR_CAPACITY);
+//   * a request with an upstream gradient (a server created with backward)
+//     also runs the adjoint in its batch: such batches replay a second graph
+//     that appends the adjoint kernels, which skip the batch's forward-only
+//     requests;
+//   * a request marked share that repeats an earlier request of the batch
+//     (same stream, n and camera) reads that request's projection and a copy
+//     of its sorted tile lists instead of projecting and sorting again; a
+//     kernel compares the two requests' geometry bytes and a request whose
+//     geometry differs is re-admitted to render on its own.
 // Latency of a request = completion observed by the scheduler - submit.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <mutex>
 #include <new>
@@ -52,6 +62,8 @@ struct Ticket {
   int32_t status = TG_PENDING;
   int32_t batch_size = 0, slot = -1, retries = 0;
   bool solo = false;             // re-admitted after an overflow: run alone
+  bool no_share = false;         // re-admitted after a geometry mismatch: project and sort itself
+  bool shared = false;           // rendered with an earlier request's projection and lists
   int64_t footprint = 0;
   int64_t t_submit = 0, t_launch = 0, t_done = 0;
 };
@@ -95,6 +107,8 @@ struct Slot {
   tg::FrameDev* dev_host = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_fb = nullptr;       // forward + adjoint
+  hipGraphExec_t exec_fb = nullptr;
   bool busy = false;
   std::vector<uint64_t> tickets;
 };
@@ -144,10 +158,41 @@ int64_t keys_est(const tg_server* s, int64_t n) {
 }
 
 // device bytes a request occupies while in flight: its share of the slot
-// workspace and its outputs
+// workspace (with the adjoint's accumulators when it asks for gradients)
+// and its outputs
 int64_t footprint_of(const tg_server* s, const tg_request& r) {
   const int64_t px = (int64_t)r.cam.width * r.cam.height;
-  return tg::padded(r.g.n) * 76 + keys_est(s, r.g.n) * 20 + px * (8 + 4 * ((int64_t)s->opts.c + 1));
+  const int64_t per_g = r.d_feat ? 76 + 24 : 76;
+  return tg::padded(r.g.n) * per_g + keys_est(s, r.g.n) * 20 + px * (8 + 4 * ((int64_t)s->opts.c + 1));
+}
+
+// Clear the per-batch device flags.
+__global__ void k_batch_reset(tg::FrameDev* d) { d->geom_mismatch = 0ull; }
+
+// Byte comparison of the geometry of every sharing request with its
+// source's (mean, scale, quat, opacity; n is equal by admission): bit r of
+// geom_mismatch is set when request r's geometry differs.
+__global__ void __launch_bounds__(256) k_geom_check(tg::BatchArgs a) {
+  const tg::BatchHdr h = tg::batch_hdr(a);
+  if (h.n_shared == 0) return;
+  for (int r = 0; r < h.n_req; ++r) {
+    const tg::ReqDev& q = a.table[r];
+    if (q.src == 0) continue;
+    const tg::ReqDev& p = a.table[q.src - 1];
+    const int64_t n = q.n;
+    bool diff = false;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        diff |= __float_as_uint(q.mean[k * n + i]) != __float_as_uint(p.mean[k * n + i]);
+        diff |= __float_as_uint(q.scale[k * n + i]) != __float_as_uint(p.scale[k * n + i]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) diff |= __float_as_uint(q.quat[k * n + i]) != __float_as_uint(p.quat[k * n + i]);
+      diff |= __float_as_uint(q.opacity[i]) != __float_as_uint(p.opacity[i]);
+    }
+    if (__syncthreads_or(diff) && threadIdx.x == 0) atomicOr(&a.dev->geom_mismatch, 1ull << r);
+  }
 }
 
 tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
@@ -174,8 +219,9 @@ tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
   return b;
 }
 
-// the batch's work on the slot stream: table upload, every step, status download
-hipError_t enqueue_batch(const tg_server* s, const Slot& sl) {
+// the batch's work on the slot stream: table upload, every step (and the
+// adjoint with `backward`), status download
+hipError_t enqueue_batch(const tg_server* s, const Slot& sl, bool backward) {
   hipError_t e;
   if ((e = hipMemcpyAsync(sl.table_dev, sl.table_host, sizeof(tg::ReqDev) * tg::MAX_BATCH,
                           hipMemcpyHostToDevice, sl.stream)) != hipSuccess)
@@ -184,16 +230,38 @@ hipError_t enqueue_batch(const tg_server* s, const Slot& sl) {
                           sl.stream)) != hipSuccess)
     return e;
   const tg::BatchArgs a = slot_args(s, sl);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, sl.stream, sl.dev);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_geom_check, dim3(1024), dim3(256), 0, sl.stream, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = tg::launch_project(a, s->cap_gauss, sl.stream)) != hipSuccess) return e;
   if ((e = tg::launch_bin_sort(a, s->cap_gauss, s->cap_tiles, s->max_tiles_req, sl.stream)) != hipSuccess)
     return e;
   if ((e = tg::launch_render_fwd(a, s->opts.c, s->cap_tiles, sl.stream)) != hipSuccess) return e;
+  if (backward && (e = tg::launch_render_bwd(a, s->opts.c, s->cap_gauss, s->cap_tiles, sl.stream)) != hipSuccess)
+    return e;
   return hipMemcpyAsync(sl.dev_host, sl.dev, sizeof(tg::FrameDev), hipMemcpyDeviceToHost, sl.stream);
+}
+
+// capture one batch sequence into a graph (replays read the table the first node uploads)
+bool capture(const tg_server* s, Slot& sl, bool backward, hipGraph_t* graph, hipGraphExec_t* exec) {
+  if (hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  const hipError_t e = enqueue_batch(s, sl, backward);
+  hipGraph_t gr = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(sl.stream, &gr);
+  if (e != hipSuccess || e2 != hipSuccess || !gr) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return false;
+  }
+  *graph = gr;
+  return hipGraphInstantiate(exec, gr, nullptr, nullptr, 0) == hipSuccess;
 }
 
 void free_slot(Slot& sl) {
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   if (sl.graph) (void)hipGraphDestroy(sl.graph);
+  if (sl.exec_fb) (void)hipGraphExecDestroy(sl.exec_fb);
+  if (sl.graph_fb) (void)hipGraphDestroy(sl.graph_fb);
   void* d[] = {sl.xy, sl.conic_o, sl.wq, sl.ext, sl.rect, sl.depth, sl.tile_count, sl.tile_start, sl.tile_cursor,
                sl.tile_order,
                sl.keys, sl.keys_tmp, sl.sorted, sl.T_final, sl.last, sl.g2d, sl.dev, sl.table_dev,
@@ -218,7 +286,8 @@ bool alloc_slot(tg_server* s, Slot& sl) {
             dalloc(&sl.tile_count, t) && dalloc(&sl.tile_start, t + 1) && dalloc(&sl.tile_cursor, t) &&
             dalloc(&sl.tile_order, t) &&
             dalloc(&sl.keys, k) && dalloc(&sl.keys_tmp, k) && dalloc(&sl.sorted, k) &&
-            dalloc(&sl.T_final, px) && dalloc(&sl.last, px) && dalloc(&sl.g2d, 1) && dalloc(&sl.dev, 1) &&
+            dalloc(&sl.T_final, px) && dalloc(&sl.last, px) &&
+            dalloc(&sl.g2d, s->opts.backward ? 6 * g : 1) && dalloc(&sl.dev, 1) &&
             dalloc(&sl.table_dev, tg::MAX_BATCH) && dalloc(&sl.hdr_dev, 1) &&
             halloc(&sl.table_host, tg::MAX_BATCH) && halloc(&sl.hdr_host, 1) && halloc(&sl.dev_host, 1);
   if (!ok) return false;
@@ -227,19 +296,11 @@ bool alloc_slot(tg_server* s, Slot& sl) {
        hipMemset(sl.hdr_dev, 0, sizeof(tg::BatchHdr)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
   if (!ok) return false;
   std::fill_n(reinterpret_cast<char*>(sl.table_host), sizeof(tg::ReqDev) * tg::MAX_BATCH, 0);
-  *sl.hdr_host = tg::BatchHdr{0, 0, 0};
+  *sl.hdr_host = tg::BatchHdr{};
   if (s->opts.use_graph) {
-    // capture the batch sequence once; replays read the table the first node uploads
-    if (hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
-    const hipError_t e = enqueue_batch(s, sl);
-    hipGraph_t gr = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(sl.stream, &gr);
-    if (e != hipSuccess || e2 != hipSuccess || !gr) {
-      if (gr) (void)hipGraphDestroy(gr);
-      return false;
-    }
-    sl.graph = gr;
-    if (hipGraphInstantiate(&sl.exec, gr, nullptr, nullptr, 0) != hipSuccess) return false;
+    // capture the batch sequences once
+    if (!capture(s, sl, false, &sl.graph, &sl.exec)) return false;
+    if (s->opts.backward && !capture(s, sl, true, &sl.graph_fb, &sl.exec_fb)) return false;
   }
   return true;
 }
@@ -250,7 +311,8 @@ bool launch_batch(tg_server* s, int slot_id) {
   Slot& sl = s->slots[slot_id];
   std::vector<uint64_t> batch;
   int64_t sum_g = 0, sum_k = 0, sum_px = 0;
-  int32_t sum_t = 0;
+  int32_t sum_t = 0, n_shared = 0;
+  bool backward = false;
   while (!s->queue.empty() && (int)batch.size() < s->opts.max_batch) {
     Ticket& t = s->tickets[s->queue.front()];
     const int64_t ng = tg::padded(t.req.g.n), nk = keys_est(s, t.req.g.n);
@@ -273,7 +335,32 @@ bool launch_batch(tg_server* s, int slot_id) {
     r.last = sl.last + sum_px;
     r.n = t.req.g.n;
     r.g_off = sum_g;
+    r.s_off = sum_g;
     r.tile_off = sum_t;
+    r.d_img = t.req.d_feat;
+    r.d_alpha = t.req.d_alpha;
+    r.d_mean = t.req.grads.d_mean;
+    r.d_log_scale = t.req.grads.d_log_scale;
+    r.d_quat = t.req.grads.d_quat;
+    r.d_logit = t.req.grads.d_opacity_logit;
+    r.d_feat = t.req.grads.d_feat;
+    backward = backward || t.req.d_feat != nullptr;
+    // reuse of an earlier request's projection and lists: same stream, n and camera
+    t.shared = false;
+    if (t.req.share && !t.no_share && t.req.g.n > 0) {
+      for (size_t p = 0; p + 1 < batch.size(); ++p) {
+        const Ticket& o = s->tickets[batch[p]];
+        const tg::ReqDev& src = sl.table_host[p];
+        if (src.src == 0 && o.req.stream_id == t.req.stream_id && o.req.g.n == t.req.g.n &&
+            std::memcmp(&o.req.cam, &t.req.cam, sizeof(tg_camera)) == 0) {
+          r.src = (int32_t)p + 1;
+          r.s_off = src.g_off;
+          t.shared = true;
+          ++n_shared;
+          break;
+        }
+      }
+    }
     tg::CamArgs& c = r.cam;
     for (int i = 0; i < 9; ++i) c.R[i] = t.req.cam.R[i];
     for (int i = 0; i < 3; ++i) c.t[i] = t.req.cam.t[i];
@@ -286,11 +373,11 @@ bool launch_batch(tg_server* s, int slot_id) {
     if (t.solo) break;
   }
   if (batch.empty()) return false;
-  *sl.hdr_host = tg::BatchHdr{(int32_t)batch.size(), sum_t, sum_g};
+  *sl.hdr_host = tg::BatchHdr{(int32_t)batch.size(), sum_t, sum_g, n_shared, 0};
   const int64_t t0 = now_ns();
   hipError_t e = hipSuccess;
-  if (s->opts.use_graph) e = hipGraphLaunch(sl.exec, sl.stream);
-  else e = enqueue_batch(s, sl);
+  if (s->opts.use_graph) e = hipGraphLaunch(backward ? sl.exec_fb : sl.exec, sl.stream);
+  else e = enqueue_batch(s, sl, backward);
   if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
   for (uint64_t id : batch) {
     Ticket& t = s->tickets[id];
@@ -316,14 +403,21 @@ bool launch_batch(tg_server* s, int slot_id) {
 // Retire a finished slot.  Called with the lock held.
 void finish_slot(tg_server* s, Slot& sl) {
   const bool over = sl.dev_host->overflow != 0;
+  const unsigned long long mismatch = sl.dev_host->geom_mismatch;
   const int64_t t1 = now_ns();
   std::vector<uint64_t> retry;
-  for (uint64_t id : sl.tickets) {
+  for (size_t k = 0; k < sl.tickets.size(); ++k) {
+    const uint64_t id = sl.tickets[k];
     Ticket& t = s->tickets[id];
     s->budget_used -= t.footprint;
     if (over && sl.tickets.size() > 1) {
       t.retries += 1;
       t.solo = true;
+      retry.push_back(id);
+    } else if (!over && ((mismatch >> k) & 1ull)) {
+      // its geometry differs from the request it shared: render it on its own
+      t.retries += 1;
+      t.no_share = true;
       retry.push_back(id);
     } else {
       t.status = over ? TG_ERR_CAPACITY : TG_OK;
@@ -408,7 +502,7 @@ tg_status tg_serve_create(tg_ctx* ctx, const tg_serve_opts* opts, tg_server** ou
       o.max_gauss_per_batch < 1 || o.max_keys_per_batch < 1 || o.max_keys_per_batch >= ((int64_t)1 << 31) ||
       o.max_pixels_per_batch < 1 || o.max_side < 1 || o.max_side > 65535 * tg::TILE || o.budget_bytes <= 0 ||
       !(o.c == 8 || o.c == 16 || o.c == 32 || o.c == 64) || !(o.keys_per_gaussian > 0.f) ||
-      o.batch_window_us < 0 || o.batch_window_us > 1000000 ||
+      o.batch_window_us < 0 || o.batch_window_us > 1000000 || (o.backward != 0 && o.backward != 1) ||
       o.max_gauss_per_batch >= ((int64_t)1 << 31))
     return TG_ERR_INVALID;
   const int device = tg::ctx_device(ctx);
@@ -475,6 +569,8 @@ tg_status tg_serve_submit(tg_server* s, const tg_request* req, uint64_t* ticket)
       !req->out_feat || req->cam.width <= 0 || req->cam.height <= 0 || req->cam.width > s->opts.max_side ||
       req->cam.height > s->opts.max_side)
     return TG_ERR_INVALID;
+  // an adjoint needs a server built for it, and feature gradients unless the set is empty
+  if (req->d_feat && (!s->opts.backward || (g.n > 0 && !req->grads.d_feat))) return TG_ERR_INVALID;
   Ticket t;
   t.req = *req;
   t.footprint = footprint_of(s, *req);
@@ -498,6 +594,8 @@ static void fill_result(const Ticket& t, tg_result* out) {
   out->batch_size = t.batch_size;
   out->slot = t.slot;
   out->retries = t.retries;
+  out->shared = t.shared ? 1 : 0;
+  out->pad = 0;
   out->t_submit_ns = t.t_submit;
   out->t_launch_ns = t.t_launch;
   out->t_done_ns = t.t_done;

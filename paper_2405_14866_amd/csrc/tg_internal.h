@@ -21,6 +21,11 @@
 //                                  (empty: x0 > x1)
 //                 depth   uint32   IEEE bits of the float32 view depth
 //                 g2d     float    [6][cap] backward accumulators
+//   A request may share the projection and sorted lists of an earlier
+//   request of the same batch whose geometry and camera are byte-identical
+//   (src > 0): it keeps its own index range (its adjoint accumulators live
+//   there) and its own tiles (its outputs and work items), but reads the 2D
+//   state of the source's range (s_off) and a copy of the source's lists.
 //   per tile      count, start[n_tiles + 1], cursor       int32
 //                 order   int32    tiles by descending key count (the blend's
 //                                  work queue hands out the longest first)
@@ -50,6 +55,7 @@ struct FrameDev {
   int32_t bwd_done;             // backward workgroups finished (the last one resets both)
   int32_t pad;
   int64_t n_keys;               // keys needed by the last binning
+  unsigned long long geom_mismatch;  // bit r: request r shares a source whose geometry differs
   // work of the last counted render
   unsigned long long n_eval;        // (pixel, Gaussian) pairs the per-pixel walk visits
   unsigned long long n_blend;       // (pixel, Gaussian) pairs blended
@@ -86,8 +92,9 @@ struct ReqDev {
   float* d_feat;         // [n][c]
   int64_t n;
   int64_t g_off;         // first global Gaussian index (multiple of BIN_CHUNK)
+  int64_t s_off;         // first global index of the 2D state it reads (g_off, or its source's)
   int32_t tile_off;      // first global tile
-  int32_t pad;
+  int32_t src;           // 0, or 1 + the batch index of the request whose projection and lists it shares
   CamArgs cam;
 };
 
@@ -96,6 +103,8 @@ struct BatchHdr {
   int32_t n_req;
   int32_t n_tiles;       // sum of the requests' tiles
   int64_t g_end;         // end of the padded global Gaussian index space
+  int32_t n_shared;      // requests that share an earlier request's projection and lists
+  int32_t pad;
 };
 
 // Kernel arguments shared by every step.  A single render passes its

@@ -16,7 +16,14 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Context", "Frame", "Rasterizer", "rasterize", "camera_struct", "GaussianSoA"]
+__all__ = ["Context", "Frame", "Rasterizer", "rasterize", "camera_struct", "GaussianSoA", "empty_grads"]
+
+
+def empty_grads(n: int, c: int, device="cuda") -> dict:
+    """Gradient buffers of one Gaussian set, SoA like the inputs: mean [3, N],
+    log_scale [3, N], quat [4, N], opacity_logit [N], feat [N, C]."""
+    f = lambda *shape: torch.empty(shape, dtype=torch.float32, device=device)
+    return dict(mean=f(3, n), log_scale=f(3, n), quat=f(4, n), opacity_logit=f(n), feat=f(n, c))
 
 
 def camera_struct(cam) -> N.tg_camera:
@@ -176,12 +183,7 @@ class Rasterizer:
         """Gradients w.r.t. the raw parameters of the last forward, SoA:
         dict(mean [3, N], log_scale [3, N], quat [4, N], opacity_logit [N],
         feat [N, C])."""
-        dev = g.mean.device
-        out = dict(mean=torch.empty((3, g.n), dtype=torch.float32, device=dev),
-                   log_scale=torch.empty((3, g.n), dtype=torch.float32, device=dev),
-                   quat=torch.empty((4, g.n), dtype=torch.float32, device=dev),
-                   opacity_logit=torch.empty((g.n,), dtype=torch.float32, device=dev),
-                   feat=torch.empty((g.n, g.c), dtype=torch.float32, device=dev))
+        out = empty_grads(g.n, g.c, g.mean.device)
         gr = N.tg_grads()
         gr.d_mean, gr.d_log_scale, gr.d_quat = _ptr(out["mean"]), _ptr(out["log_scale"]), _ptr(out["quat"])
         gr.d_opacity_logit, gr.d_feat = _ptr(out["opacity_logit"]), _ptr(out["feat"])

@@ -23,6 +23,7 @@ class Result:
         self.batch_size = int(r.batch_size)
         self.slot = int(r.slot)
         self.retries = int(r.retries)
+        self.shared = bool(r.shared)
         self.t_submit_ns = int(r.t_submit_ns)
         self.t_launch_ns = int(r.t_launch_ns)
         self.t_done_ns = int(r.t_done_ns)
@@ -43,7 +44,7 @@ class Server:
                  max_batch: int = 16, max_gauss_per_batch: int = 8_000_000,
                  max_keys_per_batch: int = 40_000_000, max_pixels_per_batch: int = 16 << 20,
                  max_side: int = 1024, use_graph: bool = True, keys_per_gaussian: float = 5.0,
-                 batch_window_us: int = 0):
+                 batch_window_us: int = 0, backward: bool = False):
         self.device = int(device)
         self.c = int(c)
         self.ctx = Context.get(self.device)
@@ -53,6 +54,7 @@ class Server:
         o.max_pixels_per_batch, o.max_side, o.c = int(max_pixels_per_batch), int(max_side), int(c)
         o.use_graph, o.keys_per_gaussian = int(bool(use_graph)), float(keys_per_gaussian)
         o.batch_window_us = int(batch_window_us)
+        o.backward = int(bool(backward))
         self.opts = o
         self.handle = N.tg_serve_create(self.ctx.handle, o)
         self._keep = {}      # ticket -> objects that must outlive the request
@@ -74,10 +76,17 @@ class Server:
         return N.tg_serve_stream_arena(self.handle, stream_id, max_n)
 
     def submit(self, g, cam, out_feat: torch.Tensor, out_alpha: Optional[torch.Tensor] = None,
-               bg: Optional[torch.Tensor] = None, stream_id: int = 0, n: Optional[int] = None) -> int:
+               bg: Optional[torch.Tensor] = None, stream_id: int = 0, n: Optional[int] = None,
+               d_feat: Optional[torch.Tensor] = None, d_alpha: Optional[torch.Tensor] = None,
+               grads: Optional[dict] = None, share: bool = False) -> int:
         """Queue one render; g is a GaussianSoA or a tg_gaussians (arena).
-        n renders only the first n Gaussians.  Returns the ticket; raises
-        TgError when the request is rejected."""
+        n renders only the first n Gaussians.  With d_feat (a server built
+        with backward) the request also runs the adjoint and writes the
+        gradients into `grads` (device tensors keyed mean, log_scale, quat,
+        opacity_logit, feat, SoA as in Rasterizer.backward).  share lets it
+        reuse the projection and sorted lists of an earlier request of the
+        same batch and stream with identical geometry and camera.  Returns
+        the ticket; raises TgError when the request is rejected."""
         req = N.tg_request()
         req.stream_id = int(stream_id)
         gs = g.struct() if isinstance(g, GaussianSoA) else g
@@ -90,9 +99,16 @@ class Server:
         req.bg = _ptr(bg)
         req.out_feat = _ptr(out_feat)
         req.out_alpha = _ptr(out_alpha)
+        req.d_feat = _ptr(d_feat)
+        req.d_alpha = _ptr(d_alpha)
+        if grads is not None:
+            req.grads.d_mean, req.grads.d_log_scale = _ptr(grads.get("mean")), _ptr(grads.get("log_scale"))
+            req.grads.d_quat, req.grads.d_opacity_logit = _ptr(grads.get("quat")), _ptr(grads.get("opacity_logit"))
+            req.grads.d_feat = _ptr(grads.get("feat"))
+        req.share = int(bool(share))
         st, ticket = N.tg_serve_submit(self.handle, req)
         N.check(st, "tg_serve_submit")
-        self._keep[ticket] = (g, out_feat, out_alpha, bg)
+        self._keep[ticket] = (g, out_feat, out_alpha, bg, d_feat, d_alpha, grads)
         return ticket
 
     def poll(self, ticket: int):

@@ -304,3 +304,72 @@ def test_serving_requests_at_full_size():
     rep = compare_forward(dict(feat=f, alpha=a, last=np.zeros_like(a, dtype=np.int32)), ora,
                           check_last=False)
     print("served request", k, reqs[k].n, rep)
+
+
+def _plain_fwd_bwd(sc, dF, torch):
+    """Plain frame-path forward and adjoint of one request (numpy outputs)."""
+    from paper_2405_14866_amd.rasterize import GaussianSoA, Rasterizer
+    g = GaussianSoA.from_scene(sc)
+    r = Rasterizer(0, max_n=sc.n, max_w=sc.cam.width, max_h=sc.cam.height)
+    f, a = r.forward(g, sc.cam)
+    T, _ = r.pixel_state(sc.cam)
+    gr = r.backward(g, torch.as_tensor(dF, device="cuda"))
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), a.cpu().numpy(), {k: v.cpu().numpy() for k, v in gr.items()}, T.cpu().numpy()
+
+
+def test_backward_in_the_loop_and_shared_sort():
+    """Adjoints served in the batch, mixed with a forward-only request, and
+    the reuse of an earlier request's projection and sorted lists: frame 1
+    of stream 0 repeats frame 0's geometry (separate device copies, byte for
+    byte equal) with new features and shares its sort; frame 2 of stream 0
+    differs by one float in one mean and asks to share too, so the device
+    check sends it back to render on its own.  Every image equals its plain
+    render bit for bit; every gradient matches the plain adjoint within the
+    gradient bar, and one shared request's gradients match the oracle."""
+    torch = torch_cuda()
+    from paper_2405_14866_amd.rasterize import GaussianSoA, empty_grads
+    from paper_2405_14866_amd.serve import Server
+    from gpu_common import compare_backward, compare_grads
+    c = 32
+    base, other, fwd_only = _requests(3, c=c, seed=500)
+    rng = np.random.default_rng(501)
+    f1 = (base.feat + 0.05 * rng.standard_normal(base.feat.shape)).astype(np.float32)
+    frame1 = scenes.Scene(base.mean, base.scale, base.quat, base.opacity, f1, base.cam, name="frame1")
+    mean2 = base.mean.copy()
+    mean2[0, 17] = np.nextafter(mean2[0, 17], np.float32(1))
+    frame2 = scenes.Scene(mean2, base.scale, base.quat, base.opacity, f1[::-1].copy(), base.cam, name="frame2")
+    reqs = [(base, 0, True, False), (frame1, 0, True, True), (fwd_only, 1, False, False),
+            (frame2, 0, True, True), (other, 2, True, False)]
+    ups = [scenes.make_cfg3_upstream(510 + k, c, sc.cam.height, sc.cam.width) for k, (sc, *_r) in enumerate(reqs)]
+    srv = Server(0, c=c, slots=1, max_batch=len(reqs), max_gauss_per_batch=120000, max_keys_per_batch=1200000,
+                 max_pixels_per_batch=len(reqs) * 128 * 128, max_side=128, batch_window_us=300000,
+                 backward=True)
+    gs = [GaussianSoA.from_scene(sc) for sc, *_r in reqs]
+    outs = [(torch.empty((c, sc.cam.height, sc.cam.width), device="cuda"),
+             torch.empty((sc.cam.height, sc.cam.width), device="cuda")) for sc, *_r in reqs]
+    grads = [empty_grads(sc.n, c) if bwd else None for sc, _s, bwd, _sh in reqs]
+    dFs = [torch.as_tensor(u, device="cuda") for u in ups]
+    torch.cuda.synchronize()
+    print("[gpu] serve: adjoints in the loop, shared sort", flush=True)
+    tickets = [srv.submit(g, sc.cam, f, a, stream_id=sid, d_feat=dF if bwd else None, grads=gr, share=sh)
+               for (sc, sid, bwd, sh), g, (f, a), gr, dF in zip(reqs, gs, outs, grads, dFs)]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert all(r.status == 0 for r in results), [r.status for r in results]
+    assert [r.shared for r in results] == [False, True, False, False, False], [r.shared for r in results]
+    assert results[3].retries == 1 and results[1].retries == 0
+    assert max(r.batch_size for r in results) >= 4
+    for k, ((sc, _s, bwd, _sh), (f, a)) in enumerate(zip(reqs, outs)):
+        pf, pa, pg, _ = _plain_fwd_bwd(sc, ups[k], torch)
+        assert np.array_equal(f.cpu().numpy(), pf) and np.array_equal(a.cpu().numpy(), pa), k
+        if bwd:
+            got = {kk: v.cpu().numpy() for kk, v in grads[k].items()}
+            compare_grads(got, pg, np.zeros(0, np.int64))
+    # the shared request against the oracle's FP64 adjoint
+    got = {kk: v.cpu().numpy() for kk, v in grads[1].items()}
+    pf, pa, _, pT = _plain_fwd_bwd(frame1, ups[1], torch)
+    ora = oracle.Oracle(frame1)
+    ref = ora.render()
+    gpu = dict(feat=pf, T=pT)
+    print("shared request vs oracle", compare_backward(got, gpu, ora, ups[1], ref_fwd=ref))
