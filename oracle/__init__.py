@@ -50,6 +50,8 @@ def _load():
     lib.tgo_pixel_walk.argtypes = [P, ct.c_int, ct.c_int, P, ct.c_int]
     lib.tgo_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
     lib.tgo_fd.argtypes = [P, P, P, P, ct.c_int64, P, ct.c_double, P, P]
+    lib.tgo_lift.restype = ct.c_int64
+    lib.tgo_lift.argtypes = [ct.c_int, ct.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -226,3 +228,38 @@ def analytic_as_matrix(grads: dict, sel) -> np.ndarray:
                            grads["quat"][:, sel].T,
                            grads["opacity_logit"][sel][:, None],
                            grads["feat"][sel]], 1)
+
+
+def lift(views, use_depth=None):
+    """Gaussians lifted from source views (scenes.SourceView list) by the
+    oracle, FP64: dict(mean [3, n], scale [3, n], quat [4, n] (identity),
+    opacity [n], feat [n, c]) in (view, row-major pixel) order.  use_depth:
+    optional list of [H, W] depth maps given instead of the disparities."""
+    lib = _load()
+    nv = len(views)
+    c = views[0].c
+    keep = []
+
+    def arr(x, dt=np.float64):
+        a = np.ascontiguousarray(x, dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    def ptrs(xs, dt=np.float64):
+        return (ct.c_void_p * nv)(*[arr(x, dt) for x in xs])
+
+    cams = np.concatenate([cam_vector(v.cam) for v in views])
+    disp = None if use_depth is not None else ptrs([v.disparity for v in views])
+    depth = ptrs(use_depth) if use_depth is not None else None
+    mask = ptrs([v.mask for v in views], np.uint8)
+    feat = ptrs([v.feat for v in views])
+    scale = ptrs([v.scale for v in views])
+    opac = ptrs([v.opacity for v in views])
+    base = np.array([v.baseline for v in views], np.float64)
+    args = [nv, c, _p(cams), disp, depth, mask, feat, scale, opac, _p(base)]
+    n = int(lib.tgo_lift(*args, None, None, None, None))
+    out = dict(mean=np.empty((3, n)), scale=np.empty((3, n)), opacity=np.empty(n), feat=np.empty((n, c)))
+    lib.tgo_lift(*args, _p(out["mean"]), _p(out["scale"]), _p(out["opacity"]), _p(out["feat"]))
+    q = np.zeros((4, n)); q[0] = 1.0
+    out["quat"] = q
+    return out

@@ -560,6 +560,58 @@ void pixel_adjoint(const Ctx& k, const std::vector<Contrib>& cb, double Tfin, co
 
 }  // namespace
 
+// ------------------------------------------------- lifting source views
+// The step upstream of the rasterizer (§4.1: each predicted disparity map is
+// converted to a depth map; §4.2: given the camera parameters, Gaussian
+// positions are unprojected from the depth maps, and the foreground pixels
+// of the source views become pixel-aligned Gaussians whose feature, scale
+// and opacity are the encoder's per-pixel maps; their rotation is fixed to
+// identity).  For a rectified stereo pair the depth of a pixel with
+// disparity d is z = f_x B / d (B the baseline); a pixel is lifted when it
+// is foreground and its disparity (or depth) is positive.
+struct LiftView {
+  CamD cam;                 // world -> camera x_c = R x_w + t; fx, fy, cx, cy; W, H
+  const double* disparity;  // [H][W] or null (then depth)
+  const double* depth;      // [H][W]
+  const uint8_t* mask;      // [H][W] foreground != 0
+  const double* feat;       // [H][W][c]
+  const double* scale;      // [H][W][3]
+  const double* opacity;    // [H][W]
+  double baseline;
+};
+
+// Append the Gaussians of one view, pixel by pixel in row-major order.
+void lift_view(const LiftView& v, int c, std::vector<double>& mean, std::vector<double>& scale,
+               std::vector<double>& opac, std::vector<double>& feat) {
+  const CamD& k = v.cam;
+  for (int j = 0; j < k.H; ++j)
+    for (int i = 0; i < k.W; ++i) {
+      const int64_t p = (int64_t)j * k.W + i;
+      if (!v.mask[p]) continue;
+      double z;
+      if (v.disparity) {
+        const double d = v.disparity[p];
+        if (!(d > 0.0)) continue;
+        z = PLANT(12, k.fx * v.baseline / d, v.baseline / d);
+      } else {
+        z = v.depth[p];
+        if (!(z > 0.0)) continue;
+      }
+      // the camera-space point on the ray through the pixel centre at depth z
+      const double xc[3] = {(i + PLANT(13, 0.5, 0.0) - k.cx) / k.fx * z, (j + 0.5 - k.cy) / k.fy * z, z};
+      // world point: x_w = R^T (x_c - t)
+      for (int a = 0; a < 3; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < 3; ++b)
+          acc += PLANT(14, k.R[3 * b + a], k.R[3 * a + b]) * (xc[b] - k.t[b]);
+        mean.push_back(acc);
+      }
+      for (int a = 0; a < 3; ++a) scale.push_back(v.scale[3 * p + a]);
+      opac.push_back(v.opacity[p]);
+      for (int ch = 0; ch < c; ++ch) feat.push_back(v.feat[(size_t)p * c + ch]);
+    }
+}
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -948,6 +1000,42 @@ void tgo_fd(void* h, const double* bg, const double* d_img, const double* d_alph
     for (int ch = 0; ch < Cc; ++ch) res[11 + ch] = (Lf[0][ch] - Lf[1][ch]) / (2.0 * eps);
     for (int ch = Cc; ch < C; ++ch) ex[11 + ch] = 1;
   });
+}
+
+// Lift n_views source views (see lift_view).  Per view v, cams[19 v ..] is
+// the camera vector of tgo_create; disp[v] or depth[v] [H][W], mask[v]
+// [H][W], feat[v] [H][W][c], scale[v] [H][W][3], opacity[v] [H][W],
+// baseline[v].  Pass out_* = null to get the count only.  Outputs (each
+// sized for at least the count): mean [3][n], scale [3][n], opacity [n],
+// feat [n][c] with n the count (the rotation is the identity for every
+// Gaussian).  Returns the count.
+int64_t tgo_lift(int n_views, int c, const double* cams, const double* const* disp,
+                 const double* const* depth, const uint8_t* const* mask, const double* const* feat,
+                 const double* const* scale, const double* const* opac, const double* baseline,
+                 double* out_mean, double* out_scale, double* out_opac, double* out_feat) {
+  std::vector<double> m, s, o, f;
+  for (int v = 0; v < n_views; ++v) {
+    LiftView lv;
+    lv.cam = cam_from(cams + 19 * v);
+    lv.disparity = disp ? disp[v] : nullptr;
+    lv.depth = depth ? depth[v] : nullptr;
+    lv.mask = mask[v];
+    lv.feat = feat[v];
+    lv.scale = scale[v];
+    lv.opacity = opac[v];
+    lv.baseline = baseline[v];
+    lift_view(lv, c, m, s, o, f);
+  }
+  const int64_t n = (int64_t)o.size();
+  if (out_mean)
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        out_mean[a * n + i] = m[3 * i + a];
+        out_scale[a * n + i] = s[3 * i + a];
+      }
+  if (out_opac) std::copy(o.begin(), o.end(), out_opac);
+  if (out_feat) std::copy(f.begin(), f.end(), out_feat);
+  return n;
 }
 
 }  // extern "C"

@@ -30,6 +30,7 @@ __all__ = [
     "Camera", "Scene", "rot_y", "rot_x", "orbit_camera", "look_at_camera",
     "make_cfg1", "make_cfg2", "make_cfg3_upstream", "make_cfg3_scaled",
     "make_cfg4_request", "make_cfg5", "make_grid_scene", "single_gaussian_scene",
+    "SourceView", "make_source_views", "make_grid_source_view",
 ]
 
 
@@ -331,3 +332,77 @@ def single_gaussian_scene(mean, scale, quat=(1.0, 0.0, 0.0, 0.0), opacity=0.8,
         cam = Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32),
                      64.0, 64.0, 32.0, 32.0, 64, 64)
     return Scene(mean, scale, quat, op, feat, cam, None, "hand")
+
+
+# ------------------------------------------------------------ source views
+@dataclass
+class SourceView:
+    """One source view as the lifting step receives it: the stereo module's
+    disparity map (a rectified pair of baseline `baseline` metres), the
+    foreground mask and the encoder's per-pixel maps.  Arrays are numpy,
+    float32 unless noted: disparity [H, W], mask [H, W] uint8, feat [H, W, C],
+    scale [H, W, 3] (activated), opacity [H, W] (activated)."""
+    cam: Camera
+    disparity: np.ndarray
+    mask: np.ndarray
+    feat: np.ndarray
+    scale: np.ndarray
+    opacity: np.ndarray
+    baseline: float
+
+    def __post_init__(self):
+        self.cam = self.cam.as_f32()
+        self.disparity = np.ascontiguousarray(self.disparity, np.float32)
+        self.mask = np.ascontiguousarray(self.mask, np.uint8)
+        self.feat = np.ascontiguousarray(self.feat, np.float32)
+        self.scale = np.ascontiguousarray(self.scale, np.float32)
+        self.opacity = np.ascontiguousarray(self.opacity, np.float32)
+        self.baseline = float(np.float32(self.baseline))
+
+    @property
+    def c(self) -> int:
+        return int(self.feat.shape[2])
+
+
+def make_source_views(seed: int = 12, src_res: int = 512, src_fx: float = 700.0, c: int = 32,
+                      baseline: float = 0.12, yaws=(-15.0, -5.0, 5.0, 15.0)):
+    """The realistic frame's four source views as maps: the upper-body mask
+    and depth surface of make_body_scene on each view of the 30 deg arc, the
+    depth given as the disparity of a rectified pair with `baseline` metres
+    (disparity = fx B / depth, the stand-in for the stereo module's output;
+    0 outside the mask), per-pixel scale depth/fx * lognormal(0, 0.2) per
+    axis, opacity U[0.3, 1], C features N(0, 1) (the stand-in for the
+    encoder's heads).  Background pixels carry random maps too; only the mask
+    and a positive disparity select a pixel."""
+    rng = np.random.default_rng(seed)
+    mask, uu, vv = _body_mask(src_res)
+    zmap = _body_depth(uu, vv)
+    views = []
+    for yaw in yaws:
+        cam = look_at_camera(yaw, 1.2, src_fx, src_res / 2.0, src_res)
+        disp = np.where(mask, src_fx * baseline / zmap, 0.0)
+        jit = np.exp(0.2 * rng.standard_normal((src_res, src_res, 3)))
+        scale = (zmap / src_fx)[:, :, None] * jit
+        o = rng.uniform(0.3, 1.0, (src_res, src_res))
+        f = rng.standard_normal((src_res, src_res, c))
+        views.append(SourceView(cam, disp, mask.astype(np.uint8), f, scale, o, baseline))
+    return views
+
+
+def make_grid_source_view(seed: int, grid: int, n: int, c: int = 32, baseline: float = 0.1):
+    """One source view of the small-scene generator as maps: a camera at the
+    origin looking along +z (fx = fy = grid, principal point at the centre),
+    depth U[1, 2] m per pixel as a disparity map, the first `n` pixels in
+    row-major order as the foreground mask, isotropic scale
+    depth/fx * lognormal(0, 0.2), opacity U[0.05, 0.95], C features N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    fx = float(grid)
+    z = rng.uniform(1.0, 2.0, (grid, grid))
+    jit = np.exp(0.2 * rng.standard_normal((grid, grid)))
+    o = rng.uniform(0.05, 0.95, (grid, grid))
+    f = rng.standard_normal((grid, grid, c))
+    mask = (np.arange(grid * grid) < n).reshape(grid, grid).astype(np.uint8)
+    s = (z / fx) * jit
+    cam = Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), fx, fx, grid / 2.0, grid / 2.0,
+                 grid, grid)
+    return SourceView(cam, fx * baseline / z, mask, f, np.repeat(s[:, :, None], 3, 2), o, baseline)

@@ -26,6 +26,9 @@ MUTANTS = {
     9: "mean gradient uses W instead of W^T",
     10: "branch variants report T in the alpha column",
     11: "branch variants drop the T bg term",
+    12: "lifting: depth from disparity without the focal length",
+    13: "lifting: pixel corner instead of pixel centre",
+    14: "lifting: camera rotation not transposed",
 }
 
 
@@ -38,6 +41,7 @@ def test_pins_catch_planted_mistake(plant, tmp_path):
     env = dict(os.environ, TGO_LIB_OVERRIDE=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_lift_pins.py"),
                         "-k", "not fd_cfg3_small"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {plant} ({MUTANTS[plant]}) survived the pins:\n{r.stdout[-2000:]}"
