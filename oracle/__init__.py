@@ -50,6 +50,7 @@ def _load():
     lib.tgo_pixel_walk.argtypes = [P, ct.c_int, ct.c_int, P, ct.c_int]
     lib.tgo_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
     lib.tgo_fd.argtypes = [P, P, P, P, ct.c_int64, P, ct.c_double, P, P]
+    lib.tgo_zsplat.argtypes = [P, P, ct.c_int64, ct.c_double, P, P]
     lib.tgo_lift.restype = ct.c_int64
     lib.tgo_lift.argtypes = [ct.c_int, ct.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
     _lib = lib
@@ -263,3 +264,15 @@ def lift(views, use_depth=None):
     q = np.zeros((4, n)); q[0] = 1.0
     out["quat"] = q
     return out
+
+
+def zsplat(mean, cam, baseline=0.0):
+    """Z-buffer of the points mean [3, n] (float32 values) splatted into
+    `cam`, one pixel per point, nearest view depth kept: (zbuf [H, W] float32,
+    +inf where empty; disparity [H, W] float32 = fx B / z, 0 where empty)."""
+    m = _f64(mean)
+    n = m.shape[1] if m.ndim == 2 else 0
+    zb = np.empty((int(cam.height), int(cam.width)), np.float32)
+    dp = np.empty_like(zb)
+    _load().tgo_zsplat(_p(cam_vector(cam)), _p(m), n, float(baseline), _p(zb), _p(dp))
+    return zb, dp

@@ -612,6 +612,36 @@ void lift_view(const LiftView& v, int c, std::vector<double>& mean, std::vector<
     }
 }
 
+// ------------------------------------------------------ z-buffer splat
+// The cascaded disparity initialisation (§4.1): the point cloud lifted from
+// cam0's depth is rasterized into the viewpoint of another camera, the
+// z-buffer (the nearest depth per pixel) is extracted and converted back to
+// a disparity map.  Reading: each point is a one-pixel splat; it lands in
+// the pixel (floor(u), floor(v)) that contains its projection and competes
+// there with its view depth t_z; points with t_z <= znear or outside the
+// image land nowhere.  The pixel and the depth are discrete decisions, taken
+// in float32 with the operation order of the binning spec (a)-(c) so that
+// they are reproducible bit for bit; disparity = fx B / z in FP64, rounded
+// to float32, and 0 where no point landed.
+struct SplatHit { bool ok; int i, j; float z; };
+
+SplatHit splat_point(const CamF& c, const float mu[3]) {
+  SplatHit h{false, 0, 0, 0.f};
+  const float tx = ((c.R[0] * mu[0] + c.R[1] * mu[1]) + c.R[2] * mu[2]) + c.t[0];
+  const float ty = ((c.R[3] * mu[0] + c.R[4] * mu[1]) + c.R[5] * mu[2]) + c.t[1];
+  const float tz = ((c.R[6] * mu[0] + c.R[7] * mu[1]) + c.R[8] * mu[2]) + c.t[2];
+  if (!(tz > c.znear)) return h;
+  const float u = (c.fx * tx) / tz + c.cx;
+  const float v = (c.fy * ty) / tz + c.cy;
+  const float fi = std::floor(PLANT(15, u, u + 0.5f)), fj = std::floor(v);
+  if (!(fi >= 0.0f && fi < (float)c.W && fj >= 0.0f && fj < (float)c.H)) return h;
+  h.ok = true;
+  h.i = (int)fi;
+  h.j = (int)fj;
+  h.z = tz;
+  return h;
+}
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -1036,6 +1066,27 @@ int64_t tgo_lift(int n_views, int c, const double* cams, const double* const* di
   if (out_opac) std::copy(o.begin(), o.end(), out_opac);
   if (out_feat) std::copy(f.begin(), f.end(), out_feat);
   return n;
+}
+
+// Z-buffer of n points (mean [3][n], float32 values given as FP64) in the
+// camera `cam` (camera vector of tgo_create): zbuf [H][W] float32 (+inf where
+// no point landed) and, if disp is not null, disparity [H][W] float32
+// (fx B / z, 0 where empty).
+void tgo_zsplat(const double* cam, const double* mean, int64_t n, double baseline, float* zbuf,
+                float* disp) {
+  const CamF c = to_f32(cam_from(cam));
+  const int64_t P = (int64_t)c.W * c.H;
+  for (int64_t p = 0; p < P; ++p) zbuf[p] = INFINITY;
+  for (int64_t k = 0; k < n; ++k) {
+    const float mu[3] = {(float)mean[k], (float)mean[n + k], (float)mean[2 * n + k]};
+    const SplatHit h = splat_point(c, mu);
+    if (!h.ok) continue;
+    float& z = zbuf[(int64_t)h.j * c.W + h.i];
+    if (PLANT(16, h.z < z, true)) z = h.z;
+  }
+  if (disp)
+    for (int64_t p = 0; p < P; ++p)
+      disp[p] = std::isinf(zbuf[p]) ? 0.0f : (float)((double)c.fx * (double)(float)baseline / (double)zbuf[p]);
 }
 
 }  // extern "C"

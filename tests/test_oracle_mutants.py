@@ -29,6 +29,8 @@ MUTANTS = {
     12: "lifting: depth from disparity without the focal length",
     13: "lifting: pixel corner instead of pixel centre",
     14: "lifting: camera rotation not transposed",
+    15: "z-buffer: a point lands in the pixel whose centre is nearest",
+    16: "z-buffer: the last point wins instead of the nearest",
 }
 
 
@@ -42,6 +44,7 @@ def test_pins_catch_planted_mistake(plant, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_lift_pins.py"),
+                        os.path.join(ROOT, "tests", "test_zsplat_pins.py"),
                         "-k", "not fd_cfg3_small"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {plant} ({MUTANTS[plant]}) survived the pins:\n{r.stdout[-2000:]}"
