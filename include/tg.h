@@ -217,6 +217,97 @@ tg_status tg_frame_pixel_state(tg_frame* frame, float* T_final, int32_t* last, v
 tg_status tg_render_noalloc(tg_ctx* ctx, const tg_gaussians* g, const tg_camera* cam, const float* bg,
                             float* out_feat, float* out_alpha, int32_t* status, void* stream);
 
+/* ------------------------------------------------ lifting source views
+ * The step upstream of the rasterizer, on the device.  §4.1 converts each
+ * source view's disparity map to depth (a rectified pair of baseline B:
+ * depth z = fx B / d for a disparity of d pixels); §4.2 unprojects the depth
+ * maps with the camera parameters and makes every foreground pixel a
+ * pixel-aligned Gaussian: position = the world point on the ray through the
+ * pixel centre (i + 0.5, j + 0.5) at depth z, i.e. R^T (x_c - t) with
+ * x_c = (z (i + 0.5 - cx) / fx, z (j + 0.5 - cy) / fy, z); feature, scale
+ * and opacity = the encoder's maps at that pixel (Eq. 4); rotation = the
+ * identity quaternion (1, 0, 0, 0).  A pixel is lifted when its mask byte is
+ * non-zero and its disparity (or depth) is positive (NaN is not). */
+
+#define TG_LIFT_MAX_VIEWS 8
+
+/* One source view (host struct of device pointers).  cam is the source
+ * camera (world -> camera, as tg_camera; width x height = the maps' size;
+ * znear is not used).  Maps, row-major over pixels:
+ *   disparity [H][W] float32 pixels, or NULL: then depth [H][W] (metres)
+ *   mask      [H][W] uint8, foreground != 0
+ *   feat      [H][W][c] float32 (channels last, 16-byte aligned)
+ *   scale     [H][W][3] float32, activated
+ *   opacity   [H][W] float32, activated
+ * baseline: metres (> 0 when a disparity map is given). */
+typedef struct tg_source_view {
+  tg_camera cam;
+  const float* disparity;
+  const float* depth;
+  const uint8_t* mask;
+  const float* feat;
+  const float* scale;
+  const float* opacity;
+  float baseline;
+} tg_source_view;
+
+/* Output buffers of a Gaussian set (host struct of device pointers), each
+ * sized for cap Gaussians: mean [3][cap], scale [3][cap], quat [4][cap],
+ * opacity [cap], feat [cap][c] (16-byte aligned).  A set of n <= cap
+ * Gaussians is written in the layout of tg_gaussians with that n: mean
+ * [3][n] occupies the first 3n floats, and so on. */
+typedef struct tg_gaussian_buffers {
+  float* mean;
+  float* scale;
+  float* quat;
+  float* opacity;
+  float* feat;
+  int64_t cap;
+} tg_gaussian_buffers;
+
+typedef struct tg_lifter tg_lifter;
+
+/* Workspace of the lifting for up to max_pixels source pixels per call (the
+ * sum over its views).  Allocates device memory (TG_ERR_OOM). */
+tg_status tg_lifter_create(tg_ctx* ctx, int64_t max_pixels, tg_lifter** out);
+void tg_lifter_destroy(tg_lifter* lifter);
+
+/* Lift n_views (1..TG_LIFT_MAX_VIEWS) source views (host array) with c
+ * channels (8, 16, 32, 64) into out, in (view, row-major pixel) order.
+ * n_out: device int64 that receives the number of lifted pixels n.  If
+ * n > out->cap nothing is written to out (n_out still receives n).
+ * Enqueue only; the caller reads *n_out after the stream reaches it and
+ * passes it as tg_gaussians.n.  TG_ERR_CAPACITY (before anything is
+ * enqueued) when the views hold more pixels than the lifter. */
+tg_status tg_lift(tg_lifter* lifter, const tg_source_view* views /* host */, int32_t n_views,
+                  int32_t c, const tg_gaussian_buffers* out /* host */, int64_t* n_out, void* stream);
+
+/* ------------------------------------------------ z-buffer point splat
+ * The cascaded disparity initialisation of §4.1 (Eq. 2-3): the point cloud
+ * lifted from one source view's depth is rasterized into the viewpoints of
+ * other cameras, and each z-buffer (the nearest depth per pixel) is
+ * extracted and converted to a disparity map.  The paper gives no splat
+ * size; here a point is a one-pixel splat: it lands in the pixel
+ * (floor(u), floor(v)) containing its projection u = fx x_c / z_c + cx,
+ * v = fy y_c / z_c + cy, and the pixel keeps the smallest view depth z_c.
+ * Points with z_c <= znear or outside the image land nowhere.  Pixel and
+ * depth follow a fixed float32 operation order (the view transform and
+ * projection of the binning spec), so the z-buffer is reproducible bit for
+ * bit and does not depend on the order of the points. */
+
+#define TG_ZSPLAT_MAX_VIEWS 8
+
+/* mean [3][n] float32 world points (for instance tg_lift's output); cams
+ * (host) [n_views] target cameras (1..TG_ZSPLAT_MAX_VIEWS, znear >= 0);
+ * zbuf: float32, the n_views planes [H_k][W_k] one after the other, +inf
+ * where no point landed; disparity: NULL or float32 planes of the same
+ * layout, fx_k B_k / z (rounded from FP64), 0 where no point landed, with
+ * baselines (host) [n_views] in metres (may be NULL when disparity is).
+ * Enqueue only, on the context's device. */
+tg_status tg_zsplat(tg_ctx* ctx, const float* mean, int64_t n, const tg_camera* cams /* host */,
+                    const float* baselines /* host */, int32_t n_views, float* zbuf, float* disparity,
+                    void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request loop that renders many target views at once (the system of §5.3
  * renders every frame of every terminal through R_G, under CUDA Graphs).

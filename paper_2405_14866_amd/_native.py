@@ -30,7 +30,8 @@ EXPORTS = [
     "tg_frame_check", "tg_frame_lists", "tg_frame_pixel_state", "tg_render_fwd_counted",
     "tg_frame_work", "tg_serve_create", "tg_serve_stream_arena", "tg_serve_submit",
     "tg_serve_poll", "tg_serve_wait", "tg_serve_release", "tg_serve_destroy",
-    "tg_render_noalloc",
+    "tg_render_noalloc", "tg_lifter_create", "tg_lifter_destroy", "tg_lift",
+    "tg_zsplat",
 ]
 
 # limits of tg_render_noalloc (include/tg.h)
@@ -77,6 +78,21 @@ class tg_result(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("batch_size", ct.c_int32), ("slot", ct.c_int32),
                 ("retries", ct.c_int32), ("shared", ct.c_int32), ("pad", ct.c_int32),
                 ("t_submit_ns", ct.c_int64), ("t_launch_ns", ct.c_int64), ("t_done_ns", ct.c_int64)]
+
+
+TG_LIFT_MAX_VIEWS = 8
+TG_ZSPLAT_MAX_VIEWS = 8
+
+
+class tg_source_view(ct.Structure):
+    _fields_ = [("cam", tg_camera), ("disparity", ct.c_void_p), ("depth", ct.c_void_p),
+                ("mask", ct.c_void_p), ("feat", ct.c_void_p), ("scale", ct.c_void_p),
+                ("opacity", ct.c_void_p), ("baseline", ct.c_float)]
+
+
+class tg_gaussian_buffers(ct.Structure):
+    _fields_ = [("mean", ct.c_void_p), ("scale", ct.c_void_p), ("quat", ct.c_void_p),
+                ("opacity", ct.c_void_p), ("feat", ct.c_void_p), ("cap", ct.c_int64)]
 
 
 class TgError(RuntimeError):
@@ -139,6 +155,13 @@ def lib():
     L.tg_frame_pixel_state.argtypes = [P, P, P, P]
     L.tg_render_noalloc.restype = I
     L.tg_render_noalloc.argtypes = [P, ct.POINTER(tg_gaussians), ct.POINTER(tg_camera), P, P, P, P, P]
+    L.tg_lifter_create.restype = I
+    L.tg_lifter_create.argtypes = [P, I64, ct.POINTER(P)]
+    L.tg_lifter_destroy.argtypes = [P]
+    L.tg_lift.restype = I
+    L.tg_lift.argtypes = [P, ct.POINTER(tg_source_view), I32, I32, ct.POINTER(tg_gaussian_buffers), P, P]
+    L.tg_zsplat.restype = I
+    L.tg_zsplat.argtypes = [P, P, I64, ct.POINTER(tg_camera), ct.POINTER(ct.c_float), I32, P, P, P]
     _lib = L
     return L
 
@@ -263,3 +286,24 @@ def tg_serve_release(srv: int, ticket: int) -> int:
 
 def tg_serve_destroy(srv: int) -> None:
     lib().tg_serve_destroy(srv)
+
+
+def tg_lifter_create(ctx: int, max_pixels: int) -> int:
+    out = ct.c_void_p()
+    check(lib().tg_lifter_create(ctx, int(max_pixels), ct.byref(out)), "tg_lifter_create")
+    return out.value
+
+
+def tg_lifter_destroy(lifter: int) -> None:
+    lib().tg_lifter_destroy(lifter)
+
+
+def tg_lift(lifter: int, views, c: int, out: tg_gaussian_buffers, n_out: int, stream: int) -> int:
+    arr = (tg_source_view * len(views))(*views)
+    return lib().tg_lift(lifter, arr, len(views), int(c), ct.byref(out), n_out, stream)
+
+
+def tg_zsplat(ctx: int, mean: int, n: int, cams, baselines, zbuf: int, disparity: int, stream: int) -> int:
+    ca = (tg_camera * len(cams))(*cams)
+    ba = None if baselines is None else (ct.c_float * len(cams))(*[float(b) for b in baselines])
+    return lib().tg_zsplat(ctx, mean, int(n), ca, ba, len(cams), zbuf, disparity, stream)
