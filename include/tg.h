@@ -191,6 +191,49 @@ tg_status tg_frame_lists(tg_frame* frame, int32_t* tile_start, int32_t* sorted, 
  * -1 if none).  Either output may be NULL. */
 tg_status tg_frame_pixel_state(tg_frame* frame, float* T_final, int32_t* last, void* stream);
 
+/* ------------------------------------------------ several target views
+ * §4.2 renders the Gaussian set into the novel views of the user's left
+ * and right eyes.  A frame created with max_views > 1 renders up to
+ * max_views target cameras of one Gaussian set together: one projection
+ * launch reads each Gaussian's 44 bytes once and writes its 2D state for
+ * every view, the binning and sort run once over all views' tiles, and one
+ * blend launch renders every view.  Each view's image is bit-identical to
+ * rendering that camera alone.  The adjoint returns the gradients of the
+ * sum of the views' losses (per Gaussian, the sum of its per-view
+ * gradients). */
+
+#define TG_MAX_VIEWS 8
+
+/* As tg_frame_create, for up to max_views (1..TG_MAX_VIEWS) views of at
+ * most max_n Gaussians and max_w x max_h pixels each; max_keys counts the
+ * keys of all views together. */
+tg_status tg_frame_create_views(tg_ctx* ctx, int32_t max_views, int64_t max_n, int32_t max_w,
+                                int32_t max_h, int64_t max_keys, tg_frame** out);
+
+/* Project g into n_views cameras (host array, 1..max_views).  tg_bin_sort
+ * then bins every view; tg_frame_lists returns the lists of all views' tiles
+ * (view v's tiles follow those of views 0..v-1); tg_frame_pixel_state
+ * returns the views' pixel state one after another.  After a projection of
+ * more than one view, use tg_render_fwd_views / tg_render_bwd_views
+ * (tg_render_fwd and tg_render_bwd return TG_ERR_INVALID). */
+tg_status tg_project_views(tg_frame* frame, const tg_gaussians* g, const tg_camera* cams /* host */,
+                           int32_t n_views, void* stream);
+
+/* Blend every view of the last tg_project_views: out_feat (host array of
+ * n_views device pointers) [c][H_v][W_v], out_alpha (host array, or NULL)
+ * [H_v][W_v] (entries may be NULL); bg [c] or NULL for every view. */
+tg_status tg_render_fwd_views(tg_frame* frame, const tg_gaussians* g, const float* bg,
+                              float* const* out_feat /* host */, float* const* out_alpha /* host */,
+                              void* stream);
+
+/* Adjoint of tg_render_fwd_views for the loss summed over the views:
+ * d_feat (host array of device pointers) [c][H_v][W_v] per view, d_alpha
+ * (host array or NULL; entries may be NULL) [H_v][W_v]; the gradients in
+ * out are those of tg_render_bwd, summed over the views. */
+tg_status tg_render_bwd_views(tg_frame* frame, const tg_gaussians* g, const float* bg,
+                              const float* const* d_feat /* host */, const float* const* d_alpha /* host */,
+                              const tg_grads* out, void* stream);
+
 /* ------------------------------------------- render without allocating
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same

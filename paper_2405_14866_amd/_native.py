@@ -31,7 +31,8 @@ EXPORTS = [
     "tg_frame_work", "tg_serve_create", "tg_serve_stream_arena", "tg_serve_submit",
     "tg_serve_poll", "tg_serve_wait", "tg_serve_release", "tg_serve_destroy",
     "tg_render_noalloc", "tg_lifter_create", "tg_lifter_destroy", "tg_lift",
-    "tg_zsplat",
+    "tg_zsplat", "tg_frame_create_views", "tg_project_views", "tg_render_fwd_views",
+    "tg_render_bwd_views",
 ]
 
 # limits of tg_render_noalloc (include/tg.h)
@@ -81,6 +82,7 @@ class tg_result(ct.Structure):
 
 
 TG_LIFT_MAX_VIEWS = 8
+TG_MAX_VIEWS = 8
 TG_ZSPLAT_MAX_VIEWS = 8
 
 
@@ -162,6 +164,15 @@ def lib():
     L.tg_lift.argtypes = [P, ct.POINTER(tg_source_view), I32, I32, ct.POINTER(tg_gaussian_buffers), P, P]
     L.tg_zsplat.restype = I
     L.tg_zsplat.argtypes = [P, P, I64, ct.POINTER(tg_camera), ct.POINTER(ct.c_float), I32, P, P, P]
+    L.tg_frame_create_views.restype = I
+    L.tg_frame_create_views.argtypes = [P, I32, I64, I32, I32, I64, ct.POINTER(P)]
+    L.tg_project_views.restype = I
+    L.tg_project_views.argtypes = [P, ct.POINTER(tg_gaussians), ct.POINTER(tg_camera), I32, P]
+    L.tg_render_fwd_views.restype = I
+    L.tg_render_fwd_views.argtypes = [P, ct.POINTER(tg_gaussians), P, ct.POINTER(P), ct.POINTER(P), P]
+    L.tg_render_bwd_views.restype = I
+    L.tg_render_bwd_views.argtypes = [P, ct.POINTER(tg_gaussians), P, ct.POINTER(P), ct.POINTER(P),
+                                      ct.POINTER(tg_grads), P]
     _lib = L
     return L
 
@@ -307,3 +318,28 @@ def tg_zsplat(ctx: int, mean: int, n: int, cams, baselines, zbuf: int, disparity
     ca = (tg_camera * len(cams))(*cams)
     ba = None if baselines is None else (ct.c_float * len(cams))(*[float(b) for b in baselines])
     return lib().tg_zsplat(ctx, mean, int(n), ca, ba, len(cams), zbuf, disparity, stream)
+
+
+def _ptr_array(ptrs):
+    return None if ptrs is None else (ct.c_void_p * len(ptrs))(*ptrs)
+
+
+def tg_frame_create_views(ctx: int, max_views: int, max_n: int, max_w: int, max_h: int, max_keys: int) -> int:
+    out = ct.c_void_p()
+    check(lib().tg_frame_create_views(ctx, int(max_views), int(max_n), int(max_w), int(max_h), int(max_keys),
+                                      ct.byref(out)), "tg_frame_create_views")
+    return out.value
+
+
+def tg_project_views(frame: int, g: tg_gaussians, cams, stream: int) -> int:
+    ca = (tg_camera * len(cams))(*cams)
+    return lib().tg_project_views(frame, ct.byref(g), ca, len(cams), stream)
+
+
+def tg_render_fwd_views(frame: int, g: tg_gaussians, bg: int, out_feat, out_alpha, stream: int) -> int:
+    return lib().tg_render_fwd_views(frame, ct.byref(g), bg, _ptr_array(out_feat), _ptr_array(out_alpha), stream)
+
+
+def tg_render_bwd_views(frame: int, g: tg_gaussians, bg: int, d_feat, d_alpha, grads: tg_grads, stream: int) -> int:
+    return lib().tg_render_bwd_views(frame, ct.byref(g), bg, _ptr_array(d_feat), _ptr_array(d_alpha),
+                                     ct.byref(grads), stream)

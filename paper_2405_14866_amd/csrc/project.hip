@@ -104,17 +104,27 @@ __device__ __forceinline__ Rect spec_f32(const CamArgs& c, float mx, float my, f
   return out;
 }
 
-// One Gaussian of request q (read through a reference whose address space
-// the caller fixes, so its fields are wave-uniform scalar loads).
-__device__ __forceinline__ void project_one(const BatchArgs& a, const ReqDev& q, int64_t gi) {
-  const int64_t i = gi - q.g_off;
+// The 11 input values of one Gaussian.
+struct GaussIn {
+  float mx, my, mz, sx, sy, sz, qw, qx, qy, qz, op;
+};
+
+// Gaussian i of request q (read through a reference whose address space the
+// caller fixes, so its fields are wave-uniform scalar loads).
+__device__ __forceinline__ GaussIn load_gauss(const ReqDev& q, int64_t i) {
   const int64_t n = q.n;
-  if (i >= n) return;
-  const float mx = q.mean[i], my = q.mean[n + i], mz = q.mean[2 * n + i];
-  const float sx = q.scale[i], sy = q.scale[n + i], sz = q.scale[2 * n + i];
-  const float qw = q.quat[i], qx = q.quat[n + i], qy = q.quat[2 * n + i], qz = q.quat[3 * n + i];
-  const float op = q.opacity[i];
-  const CamArgs& c = q.cam;
+  GaussIn G;
+  G.mx = q.mean[i]; G.my = q.mean[n + i]; G.mz = q.mean[2 * n + i];
+  G.sx = q.scale[i]; G.sy = q.scale[n + i]; G.sz = q.scale[2 * n + i];
+  G.qw = q.quat[i]; G.qx = q.quat[n + i]; G.qy = q.quat[2 * n + i]; G.qz = q.quat[3 * n + i];
+  G.op = q.opacity[i];
+  return G;
+}
+
+// Project one Gaussian into camera c; the state goes to global index gi.
+__device__ __forceinline__ void project_store(const BatchArgs& a, const CamArgs& c, const GaussIn& G, int64_t gi) {
+  const float mx = G.mx, my = G.my, mz = G.mz, sx = G.sx, sy = G.sy, sz = G.sz;
+  const float qw = G.qw, qx = G.qx, qy = G.qy, qz = G.qz, op = G.op;
   const Rect rc = spec_f32(c, mx, my, mz, sx, sy, sz, qw, qx, qy, qz);
 
   uint2 rect = make_uint2(1u, 0u);   // empty
@@ -178,18 +188,35 @@ __device__ __forceinline__ void project_one(const BatchArgs& a, const ReqDev& q,
   a.depth[gi] = rc.ok ? rc.key : 0xffffffffu;
 }
 
+// TABLE: the requests come from the device table (a serving batch, the
+// views of one set); a separate instantiation from the single inline
+// request, so that the single render keeps its own register budget.
+template <bool TABLE>
 __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
-  const BatchHdr h = batch_hdr(a);
+  const BatchHdr h = TABLE ? *a.hdr_dev : a.hdr;
   // clear the per-tile key counters that the binning accumulates into
   for (int t = blockIdx.x * 256 + threadIdx.x; t < h.n_tiles; t += gridDim.x * 256) a.tile_count[t] = 0;
   const int64_t g0 = (int64_t)blockIdx.x * 256;       // 256-aligned: one request per workgroup
-  const int r = req_of_gauss(a, h, g0);
-  if (r < 0) return;
   const int64_t gi = g0 + threadIdx.x;
-  if (a.table) {                                 // a batch's table in global memory
-    if (a.table[r].src == 0) project_one(a, a.table[r], gi);   // a sharing request reads its source's state
-  } else {
-    project_one(a, a.one, gi);                   // one request in the kernel arguments
+  if (TABLE) {                                   // a batch's table in global memory
+    const int r = req_of_gauss(a, h, g0);
+    if (r < 0) return;
+    const ReqDev& q = a.table[r];
+    // a sharing request reads its source's state; a covered view is
+    // projected by the workgroups of the set's first view
+    if (q.src != 0 || q.covered) return;
+    const int64_t i = gi - q.g_off;
+    if (i >= q.n) return;
+    const GaussIn G = load_gauss(q, i);          // read once for every view of the set
+    const int nv = q.extra_views;
+    for (int v = 0; v <= nv; ++v) {
+      const ReqDev& qv = a.table[r + v];
+      project_store(a, qv.cam, G, qv.g_off + i);
+    }
+  } else {                                       // one request in the kernel arguments
+    if (g0 >= h.g_end) return;
+    const int64_t i = gi - a.one.g_off;
+    if (i < a.one.n) project_store(a, a.one.cam, load_gauss(a.one, i), gi);
   }
 }
 
@@ -198,7 +225,8 @@ __global__ void __launch_bounds__(256) k_project(BatchArgs a) {
 hipError_t launch_project(const BatchArgs& a, int64_t grid_gauss, hipStream_t s) {
   const int64_t blocks = (grid_gauss + 255) / 256;
   const int grid = (int)(blocks > 0 ? blocks : 1);
-  hipLaunchKernelGGL(k_project, dim3(grid), dim3(256), 0, s, a);
+  if (a.table) hipLaunchKernelGGL(k_project<true>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_project<false>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

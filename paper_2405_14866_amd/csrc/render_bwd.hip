@@ -326,14 +326,21 @@ hipError_t launch_bwd_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s) {
 }
 
 // ------------------------------------------------------- project backward
-// One Gaussian of request qr (read through a reference whose address
-// space the caller fixes, so its fields are wave-uniform scalar loads).
-__device__ __forceinline__ void project_bwd_one(const BatchArgs& a, const ReqDev& qr, int64_t gi) {
-  const int64_t i = gi - qr.g_off;
-  const int64_t n = qr.n;
-  if (i >= n || !qr.d_img) return;            // no adjoint asked for this request
-  const int64_t gc = a.g_cap;
+// Raw-parameter gradients of one Gaussian, accumulated in FP64.
+struct RawGrad {
   double dmu[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dlg = 0;
+};
+
+// Add the chain rule of Gaussian i of request qr (read through a reference
+// whose address space the caller fixes, so its fields are wave-uniform
+// scalar loads; its 2D gradients sit at global index gi) to g.
+__device__ __forceinline__ void project_bwd_add(const BatchArgs& a, const ReqDev& qr, int64_t i, int64_t gi,
+                                                RawGrad& g) {
+  const int64_t n = qr.n;
+  const int64_t gc = a.g_cap;
+  double* dmu = g.dmu;
+  double* dls = g.dls;
+  double* dq = g.dq;
   const uint2 r = a.rect[qr.s_off + i];       // the projection this request's render used
   const bool live = (r.x & 0xffffu) <= (r.x >> 16);
   if (live) {
@@ -408,7 +415,7 @@ __device__ __forceinline__ void project_bwd_one(const BatchArgs& a, const ReqDev
     gt[1] = gv * fy * iz - GJ[5] * fy * iz2;
     gt[2] = -gu * fx * tx * iz2 - gv * fy * ty * iz2 - GJ[0] * fx * iz2 + GJ[2] * 2.0 * fx * tx * iz3 -
             GJ[4] * fy * iz2 + GJ[5] * 2.0 * fy * ty * iz3;
-    for (int k = 0; k < 3; ++k) dmu[k] = W[k] * gt[0] + W[3 + k] * gt[1] + W[6 + k] * gt[2];
+    for (int k = 0; k < 3; ++k) dmu[k] += W[k] * gt[0] + W[3 + k] * gt[1] + W[6 + k] * gt[2];
     // Sigma3D = M M^T, M = R diag(s)
     double GM[9];
     for (int p = 0; p < 3; ++p)
@@ -421,7 +428,7 @@ __device__ __forceinline__ void project_bwd_one(const BatchArgs& a, const ReqDev
         GR[3 * p + k] = GM[3 * p + k] * s3[k];
         ds += GM[3 * p + k] * R[3 * p + k];
       }
-      dls[k] = ds * s3[k];
+      dls[k] += ds * s3[k];
     }
     double gq[4];
     gq[0] = 2 * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
@@ -433,10 +440,19 @@ __device__ __forceinline__ void project_bwd_one(const BatchArgs& a, const ReqDev
                  qy * GR[7]);
     const double dot = qw * gq[0] + qx * gq[1] + qy * gq[2] + qz * gq[3];
     const double qh[4] = {qw, qx, qy, qz};
-    for (int k = 0; k < 4; ++k) dq[k] = (gq[k] - qh[k] * dot) / nq;
+    for (int k = 0; k < 4; ++k) dq[k] += (gq[k] - qh[k] * dot) / nq;
     const double o = qr.opacity[i];
-    dlg = o * (1.0 - o) * gO;
+    g.dlg += o * (1.0 - o) * gO;
   }
+}
+
+// Write the accumulated gradients of Gaussian i of request qr.
+__device__ __forceinline__ void project_bwd_write(const ReqDev& qr, int64_t i, const RawGrad& g) {
+  const int64_t n = qr.n;
+  const double* dmu = g.dmu;
+  const double* dls = g.dls;
+  const double* dq = g.dq;
+  const double dlg = g.dlg;
   if (qr.d_mean)
     for (int k = 0; k < 3; ++k) qr.d_mean[k * n + i] = (float)dmu[k];
   if (qr.d_log_scale)
@@ -446,14 +462,32 @@ __device__ __forceinline__ void project_bwd_one(const BatchArgs& a, const ReqDev
   if (qr.d_logit) qr.d_logit[i] = (float)dlg;
 }
 
+template <bool TABLE>
 __global__ void __launch_bounds__(256) k_project_bwd(BatchArgs a) {
-  const BatchHdr h = batch_hdr(a);
+  const BatchHdr h = TABLE ? *a.hdr_dev : a.hdr;
   const int64_t g0 = (int64_t)blockIdx.x * 256;
-  const int rq = req_of_gauss(a, h, g0);
-  if (rq < 0) return;
+  if (g0 >= h.g_end) return;
   const int64_t gi = g0 + threadIdx.x;
-  if (a.table) project_bwd_one(a, a.table[rq], gi);   // a batch's table in global memory
-  else project_bwd_one(a, a.one, gi);                 // one request in the kernel arguments
+  RawGrad g;
+  if (TABLE) {                                   // a batch's table in global memory
+    const int rq = req_of_gauss(a, h, g0);
+    if (rq < 0) return;
+    const ReqDev& q = a.table[rq];
+    if (q.covered) return;                       // chained by the first view of its set
+    const int64_t i = gi - q.g_off;
+    if (i >= q.n || !q.d_img) return;            // no adjoint asked for this request
+    const int nv = q.extra_views;
+    for (int v = 0; v <= nv; ++v) {              // every view of the set: summed
+      const ReqDev& qv = a.table[rq + v];
+      project_bwd_add(a, qv, i, qv.g_off + i, g);
+    }
+    project_bwd_write(q, i, g);
+  } else {                                       // one request in the kernel arguments
+    const int64_t i = gi - a.one.g_off;
+    if (i >= a.one.n || !a.one.d_img) return;
+    project_bwd_add(a, a.one, i, gi, g);
+    project_bwd_write(a.one, i, g);
+  }
 }
 
 }  // namespace
@@ -472,7 +506,8 @@ hipError_t launch_render_bwd(const BatchArgs& a, int c, int64_t grid_gauss, int3
   }
   if (e != hipSuccess) return e;
   const int64_t blocks = (grid_gauss + 255) / 256;
-  hipLaunchKernelGGL(k_project_bwd, dim3((int)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, a);
+  if (a.table) hipLaunchKernelGGL(k_project_bwd<true>, dim3((int)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_project_bwd<false>, dim3((int)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

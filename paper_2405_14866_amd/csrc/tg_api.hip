@@ -37,13 +37,21 @@ struct tg_frame {
   int32_t* last = nullptr;
   float* g2d = nullptr;          // [6][g_cap] backward accumulators
   tg::FrameDev* dev = nullptr;
-  int64_t g_cap = 0;             // padded Gaussian capacity
+  int64_t g_cap = 0;             // padded Gaussian capacity (all views)
+  int32_t max_views = 1;
+  int64_t view_pixels = 0;       // max_w * max_h: pixel-state slice of one view
+  tg::ReqDev* table_dev = nullptr;   // request table of a multi-view projection
+  tg::BatchHdr* hdr_dev = nullptr;
   // state of the last projection / render
-  tg::ReqDev req{};
+  tg::ReqDev req{};              // the request of a single-view projection
+  tg::ReqDev views[TG_MAX_VIEWS]{};  // ... of a multi-view projection
+  int32_t n_views = 1;
   int64_t n = -1;
   int32_t c = 0;
   tg::CamArgs cam{};
-  int32_t n_tiles = 0;
+  int32_t n_tiles = 0;           // all views
+  int32_t max_req_tiles = 0;     // largest view
+  int64_t g_end = 0;             // padded index space of the last projection
   bool binned = false, rendered = false;
   hipStream_t last_stream = nullptr;
 };
@@ -54,6 +62,24 @@ hipError_t noalloc_setup(int device);   // noalloc.hip
 }  // namespace tg
 
 namespace {
+
+// The request table of a multi-view frame, copied into device memory by a
+// one-lane kernel (stream-ordered and capturable, no host synchronisation).
+struct TableUpload {
+  tg::ReqDev r[TG_MAX_VIEWS];
+  tg::BatchHdr h;
+  tg::ReqDev* dst;
+  tg::BatchHdr* hdst;
+  int32_t n;
+};
+
+__global__ void k_put_table(TableUpload t) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+#pragma unroll
+  for (int k = 0; k < TG_MAX_VIEWS; ++k)
+    if (k < t.n) t.dst[k] = t.r[k];
+  *t.hdst = t.h;
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -81,7 +107,7 @@ tg_status dalloc(T** p, size_t count) {
 void free_frame(tg_frame* f) {
   void* ptrs[] = {f->xy, f->conic_o, f->wq, f->ext, f->rect, f->depth, f->tile_count, f->tile_start,
                   f->tile_cursor, f->tile_order, f->keys, f->keys_tmp, f->sorted, f->T_final,
-                  f->last, f->g2d, f->dev};
+                  f->last, f->g2d, f->dev, f->table_dev, f->hdr_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -96,15 +122,21 @@ tg_status check_gaussians(const tg_frame* f, const tg_gaussians* g, bool need_c)
   return TG_OK;
 }
 
-// Kernel arguments of a frame: a batch of one request passed inline.
+// Kernel arguments of a frame: a batch of one request passed inline, or
+// the views of a multi-view projection through the device table.
 tg::BatchArgs frame_args(tg_frame* f) {
   tg::BatchArgs b{};
-  b.table = nullptr;
-  b.hdr_dev = nullptr;
-  b.one = f->req;
-  b.hdr.n_req = 1;
+  if (f->n_views > 1) {
+    b.table = f->table_dev;
+    b.hdr_dev = f->hdr_dev;
+  } else {
+    b.table = nullptr;
+    b.hdr_dev = nullptr;
+    b.one = f->req;
+  }
+  b.hdr.n_req = f->n_views;
   b.hdr.n_tiles = f->n_tiles;
-  b.hdr.g_end = tg::padded(f->n);
+  b.hdr.g_end = f->g_end;
   b.xy = f->xy;
   b.conic_o = f->conic_o;
   b.wq = f->wq;
@@ -123,6 +155,32 @@ tg::BatchArgs frame_args(tg_frame* f) {
   b.key_cap = f->max_keys;
   b.dev = f->dev;
   return b;
+}
+
+// Copy the frame's view table (and its header) to the device, on stream s.
+hipError_t upload_views(tg_frame* f, hipStream_t s) {
+  TableUpload t{};
+  for (int k = 0; k < f->n_views; ++k) t.r[k] = f->views[k];
+  t.h.n_req = f->n_views;
+  t.h.n_tiles = f->n_tiles;
+  t.h.g_end = f->g_end;
+  t.h.n_shared = 0;
+  t.dst = f->table_dev;
+  t.hdst = f->hdr_dev;
+  t.n = f->n_views;
+  hipLaunchKernelGGL(k_put_table, dim3(1), dim3(64), 0, s, t);
+  return hipGetLastError();
+}
+
+tg::CamArgs cam_args(const tg_camera* cam) {
+  tg::CamArgs c;
+  for (int i = 0; i < 9; ++i) c.R[i] = cam->R[i];
+  for (int i = 0; i < 3; ++i) c.t[i] = cam->t[i];
+  c.fx = cam->fx; c.fy = cam->fy; c.cx = cam->cx; c.cy = cam->cy; c.znear = cam->znear;
+  c.W = cam->width; c.H = cam->height;
+  c.tiles_x = (cam->width + tg::TILE - 1) / tg::TILE;
+  c.tiles_y = (cam->height + tg::TILE - 1) / tg::TILE;
+  return c;
 }
 
 }  // namespace
@@ -164,7 +222,13 @@ void tg_ctx_destroy(tg_ctx* ctx) { delete ctx; }
 
 tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max_h,
                           int64_t max_keys, tg_frame** out) {
-  if (!ctx || !out || max_n < 0 || max_w <= 0 || max_h <= 0 || max_keys <= 0 ||
+  return tg_frame_create_views(ctx, 1, max_n, max_w, max_h, max_keys, out);
+}
+
+tg_status tg_frame_create_views(tg_ctx* ctx, int32_t max_views, int64_t max_n, int32_t max_w,
+                                int32_t max_h, int64_t max_keys, tg_frame** out) {
+  if (!ctx || !out || max_views < 1 || max_views > TG_MAX_VIEWS || max_n < 0 || max_w <= 0 || max_h <= 0 ||
+      max_keys <= 0 ||
       max_keys >= (int64_t)1 << 31 || max_n >= (int64_t)1 << 31 || max_w > 65535 * tg::TILE ||
       max_h > 65535 * tg::TILE)
     return TG_ERR_INVALID;
@@ -179,9 +243,15 @@ tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max
   f->max_w = max_w;
   f->max_h = max_h;
   const int64_t tx = (max_w + tg::TILE - 1) / tg::TILE, ty = (max_h + tg::TILE - 1) / tg::TILE;
-  f->max_tiles = (int32_t)(tx * ty);
-  const size_t npix = (size_t)max_w * max_h;
-  f->g_cap = tg::padded(max_n > 0 ? max_n : 1);
+  if (tx * ty * max_views >= ((int64_t)1 << 31) || tg::padded(max_n > 0 ? max_n : 1) * max_views >= ((int64_t)1 << 31)) {
+    delete f;
+    return TG_ERR_INVALID;
+  }
+  f->max_views = max_views;
+  f->max_tiles = (int32_t)(tx * ty * max_views);
+  f->view_pixels = (int64_t)max_w * max_h;
+  const size_t npix = (size_t)max_w * max_h * max_views;
+  f->g_cap = tg::padded(max_n > 0 ? max_n : 1) * max_views;
   tg_status st = TG_OK;
   if (st == TG_OK) st = dalloc(&f->xy, f->g_cap);
   if (st == TG_OK) st = dalloc(&f->conic_o, f->g_cap);
@@ -200,6 +270,8 @@ tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max
   if (st == TG_OK) st = dalloc(&f->last, npix);
   if (st == TG_OK) st = dalloc(&f->g2d, (size_t)6 * f->g_cap);
   if (st == TG_OK) st = dalloc(&f->dev, 1);
+  if (st == TG_OK && max_views > 1) st = dalloc(&f->table_dev, TG_MAX_VIEWS);
+  if (st == TG_OK && max_views > 1) st = dalloc(&f->hdr_dev, 1);
   if (st == TG_OK && hipMemset(f->dev, 0, sizeof(tg::FrameDev)) != hipSuccess) st = TG_ERR_HIP;
   if (st == TG_OK && hipMemset(f->tile_start, 0, ((size_t)f->max_tiles + 1) * sizeof(int32_t)) != hipSuccess)
     st = TG_ERR_HIP;
@@ -228,16 +300,13 @@ tg_status tg_project(tg_frame* f, const tg_gaussians* g, const tg_camera* cam, v
   if (cam->width <= 0 || cam->height <= 0 || cam->width > f->max_w || cam->height > f->max_h)
     return TG_ERR_INVALID;
   DeviceGuard guard(f->device);
-  tg::CamArgs c;
-  for (int i = 0; i < 9; ++i) c.R[i] = cam->R[i];
-  for (int i = 0; i < 3; ++i) c.t[i] = cam->t[i];
-  c.fx = cam->fx; c.fy = cam->fy; c.cx = cam->cx; c.cy = cam->cy; c.znear = cam->znear;
-  c.W = cam->width; c.H = cam->height;
-  c.tiles_x = (cam->width + tg::TILE - 1) / tg::TILE;
-  c.tiles_y = (cam->height + tg::TILE - 1) / tg::TILE;
+  const tg::CamArgs c = cam_args(cam);
   f->cam = c;
   f->n = g->n;
+  f->n_views = 1;
   f->n_tiles = c.tiles_x * c.tiles_y;
+  f->max_req_tiles = f->n_tiles;
+  f->g_end = tg::padded(g->n);
   f->binned = f->rendered = false;
   tg::ReqDev& q = f->req;
   q = tg::ReqDev{};
@@ -255,7 +324,7 @@ tg_status tg_bin_sort(tg_frame* f, void* stream) {
   DeviceGuard guard(f->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   f->last_stream = s;
-  if (tg::launch_bin_sort(frame_args(f), tg::padded(f->n), f->n_tiles, f->n_tiles, s) != hipSuccess)
+  if (tg::launch_bin_sort(frame_args(f), f->g_end, f->n_tiles, f->max_req_tiles, s) != hipSuccess)
     return TG_ERR_HIP;
   f->binned = true;
   return TG_OK;
@@ -263,7 +332,7 @@ tg_status tg_bin_sort(tg_frame* f, void* stream) {
 
 static tg_status render_fwd_impl(tg_frame* f, const tg_gaussians* g, const float* bg,
                                  float* out_feat, float* out_alpha, void* stream, bool count) {
-  if (!f || !f->binned || !out_feat) return TG_ERR_INVALID;
+  if (!f || !f->binned || !out_feat || f->n_views != 1) return TG_ERR_INVALID;
   tg_status st = check_gaussians(f, g, true);
   if (st != TG_OK) return st;
   if (g->n != f->n) return TG_ERR_INVALID;
@@ -304,7 +373,7 @@ tg_status tg_frame_work(tg_frame* f, int64_t* counts, int32_t n_counts) {
 
 tg_status tg_render_bwd(tg_frame* f, const tg_gaussians* g, const float* bg, const float* d_feat,
                         const float* d_alpha, const tg_grads* out, void* stream) {
-  if (!f || !f->rendered || !d_feat || !out) return TG_ERR_INVALID;
+  if (!f || !f->rendered || !d_feat || !out || f->n_views != 1) return TG_ERR_INVALID;
   tg_status st = check_gaussians(f, g, true);
   if (st != TG_OK) return st;
   if (g->n != f->n || g->c != f->c) return TG_ERR_INVALID;
@@ -322,7 +391,7 @@ tg_status tg_render_bwd(tg_frame* f, const tg_gaussians* g, const float* bg, con
   q.d_quat = out->d_quat;
   q.d_logit = out->d_opacity_logit;
   q.d_feat = out->d_feat;
-  if (tg::launch_render_bwd(frame_args(f), g->c, tg::padded(f->n), f->n_tiles, s) != hipSuccess)
+  if (tg::launch_render_bwd(frame_args(f), g->c, f->g_end, f->n_tiles, s) != hipSuccess)
     return TG_ERR_HIP;
   return TG_OK;
 }
@@ -357,11 +426,118 @@ tg_status tg_frame_pixel_state(tg_frame* f, float* T_final, int32_t* last, void*
   if (!f || !f->rendered) return TG_ERR_INVALID;
   DeviceGuard guard(f->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t npix = (size_t)f->cam.W * f->cam.H;
-  if (T_final && hipMemcpyAsync(T_final, f->T_final, npix * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return TG_ERR_HIP;
-  if (last && hipMemcpyAsync(last, f->last, npix * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return TG_ERR_HIP;
+  size_t o = 0;
+  for (int v = 0; v < f->n_views; ++v) {
+    const tg::CamArgs& c = f->n_views > 1 ? f->views[v].cam : f->cam;
+    const size_t npix = (size_t)c.W * c.H, src = (size_t)v * f->view_pixels;
+    if (T_final && hipMemcpyAsync(T_final + o, f->T_final + src, npix * sizeof(float), hipMemcpyDeviceToDevice,
+                                  s) != hipSuccess)
+      return TG_ERR_HIP;
+    if (last && hipMemcpyAsync(last + o, f->last + src, npix * sizeof(int32_t), hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+      return TG_ERR_HIP;
+    o += npix;
+  }
+  return TG_OK;
+}
+
+tg_status tg_project_views(tg_frame* f, const tg_gaussians* g, const tg_camera* cams, int32_t n_views,
+                           void* stream) {
+  if (!f || !cams || n_views < 1 || n_views > f->max_views) return TG_ERR_INVALID;
+  if (n_views == 1) return tg_project(f, g, cams, stream);
+  tg_status st = check_gaussians(f, g, false);
+  if (st != TG_OK) return st;
+  for (int v = 0; v < n_views; ++v)
+    if (cams[v].width <= 0 || cams[v].height <= 0 || cams[v].width > f->max_w || cams[v].height > f->max_h)
+      return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  const int64_t pn = tg::padded(g->n);
+  int32_t tiles = 0, most = 0;
+  for (int v = 0; v < n_views; ++v) {
+    tg::ReqDev& q = f->views[v];
+    q = tg::ReqDev{};
+    q.mean = g->mean; q.scale = g->scale; q.quat = g->quat; q.opacity = g->opacity; q.feat = g->feat;
+    q.T_final = f->T_final + v * f->view_pixels;
+    q.last = f->last + v * f->view_pixels;
+    q.n = g->n;
+    q.g_off = v * pn;
+    q.s_off = q.g_off;
+    q.tile_off = tiles;
+    q.cam = cam_args(&cams[v]);
+    q.extra_views = v == 0 ? n_views - 1 : 0;
+    q.covered = v > 0 ? 1 : 0;
+    const int32_t t = q.cam.tiles_x * q.cam.tiles_y;
+    tiles += t;
+    most = t > most ? t : most;
+  }
+  f->cam = f->views[0].cam;
+  f->n = g->n;
+  f->n_views = n_views;
+  f->n_tiles = tiles;
+  f->max_req_tiles = most;
+  f->g_end = n_views * pn;
+  f->binned = f->rendered = false;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  f->last_stream = s;
+  if (upload_views(f, s) != hipSuccess) return TG_ERR_HIP;
+  return tg::launch_project(frame_args(f), f->g_end, s) == hipSuccess ? TG_OK : TG_ERR_HIP;
+}
+
+tg_status tg_render_fwd_views(tg_frame* f, const tg_gaussians* g, const float* bg, float* const* out_feat,
+                              float* const* out_alpha, void* stream) {
+  if (!f || !out_feat) return TG_ERR_INVALID;
+  if (f->n_views == 1) return tg_render_fwd(f, g, bg, out_feat[0], out_alpha ? out_alpha[0] : nullptr, stream);
+  if (!f->binned) return TG_ERR_INVALID;
+  tg_status st = check_gaussians(f, g, true);
+  if (st != TG_OK) return st;
+  if (g->n != f->n) return TG_ERR_INVALID;
+  for (int v = 0; v < f->n_views; ++v)
+    if (!out_feat[v]) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  for (int v = 0; v < f->n_views; ++v) {
+    tg::ReqDev& q = f->views[v];
+    q.feat = g->feat;
+    q.bg = bg;
+    q.out_feat = out_feat[v];
+    q.out_alpha = out_alpha ? out_alpha[v] : nullptr;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  f->last_stream = s;
+  f->c = g->c;
+  if (upload_views(f, s) != hipSuccess) return TG_ERR_HIP;
+  if (tg::launch_render_fwd(frame_args(f), g->c, f->n_tiles, s, false) != hipSuccess) return TG_ERR_HIP;
+  f->rendered = true;
+  return TG_OK;
+}
+
+tg_status tg_render_bwd_views(tg_frame* f, const tg_gaussians* g, const float* bg, const float* const* d_feat,
+                              const float* const* d_alpha, const tg_grads* out, void* stream) {
+  if (!f || !d_feat || !out) return TG_ERR_INVALID;
+  if (f->n_views == 1) return tg_render_bwd(f, g, bg, d_feat[0], d_alpha ? d_alpha[0] : nullptr, out, stream);
+  if (!f->rendered) return TG_ERR_INVALID;
+  tg_status st = check_gaussians(f, g, true);
+  if (st != TG_OK) return st;
+  if (g->n != f->n || g->c != f->c) return TG_ERR_INVALID;
+  if (g->n > 0 && !out->d_feat) return TG_ERR_INVALID;
+  for (int v = 0; v < f->n_views; ++v)
+    if (!d_feat[v]) return TG_ERR_INVALID;
+  DeviceGuard guard(f->device);
+  for (int v = 0; v < f->n_views; ++v) {
+    tg::ReqDev& q = f->views[v];
+    q.feat = g->feat;
+    q.bg = bg;
+    q.d_img = d_feat[v];
+    q.d_alpha = d_alpha ? d_alpha[v] : nullptr;
+    q.d_mean = out->d_mean;
+    q.d_log_scale = out->d_log_scale;
+    q.d_quat = out->d_quat;
+    q.d_logit = out->d_opacity_logit;
+    q.d_feat = out->d_feat;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  f->last_stream = s;
+  if (upload_views(f, s) != hipSuccess) return TG_ERR_HIP;
+  if (tg::launch_render_bwd(frame_args(f), g->c, f->g_end, f->n_tiles, s) != hipSuccess) return TG_ERR_HIP;
   return TG_OK;
 }
 

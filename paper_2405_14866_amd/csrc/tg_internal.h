@@ -21,6 +21,9 @@
 //                                  (empty: x0 > x1)
 //                 depth   uint32   IEEE bits of the float32 view depth
 //                 g2d     float    [6][cap] backward accumulators
+//   Views of one Gaussian set (extra_views / covered) are requests of their
+//   own (own index range, tiles and pixel state) whose Gaussian loads in
+//   the projection and its adjoint are shared.
 //   A request may share the projection and sorted lists of an earlier
 //   request of the same batch whose geometry and camera are byte-identical
 //   (src > 0): it keeps its own index range (its adjoint accumulators live
@@ -95,6 +98,12 @@ struct ReqDev {
   int64_t s_off;         // first global index of the 2D state it reads (g_off, or its source's)
   int32_t tile_off;      // first global tile
   int32_t src;           // 0, or 1 + the batch index of the request whose projection and lists it shares
+  // Several target views of one Gaussian set (a stereo pair): the views are
+  // consecutive requests with the same Gaussian pointers; the first one's
+  // projection (and projection adjoint) workgroups read each Gaussian once
+  // and serve all of them, the others are marked covered.
+  int32_t extra_views;   // the next extra_views requests are further views of this one's Gaussians
+  int32_t covered;       // 1: an earlier request projects this one (and chains its adjoint)
   CamArgs cam;
 };
 

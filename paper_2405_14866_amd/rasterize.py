@@ -101,10 +101,12 @@ class Context:
 class Frame:
     """Resident workspace of one render (see tg_frame_create)."""
 
-    def __init__(self, ctx: Context, max_n: int, max_w: int, max_h: int, max_keys: int):
+    def __init__(self, ctx: Context, max_n: int, max_w: int, max_h: int, max_keys: int, max_views: int = 1):
         self.ctx = ctx
         self.max_n, self.max_w, self.max_h, self.max_keys = int(max_n), int(max_w), int(max_h), int(max_keys)
-        self.handle = N.tg_frame_create(ctx.handle, self.max_n, self.max_w, self.max_h, self.max_keys)
+        self.max_views = int(max_views)
+        self.handle = N.tg_frame_create_views(ctx.handle, self.max_views, self.max_n, self.max_w, self.max_h,
+                                              self.max_keys)
         self.generation = 0
 
     def close(self):
@@ -118,8 +120,9 @@ class Frame:
         except Exception:
             pass
 
-    def fits(self, n, w, h, keys=0):
-        return n <= self.max_n and w <= self.max_w and h <= self.max_h and keys <= self.max_keys
+    def fits(self, n, w, h, keys=0, views=1):
+        return (n <= self.max_n and w <= self.max_w and h <= self.max_h and keys <= self.max_keys
+                and views <= self.max_views)
 
 
 class Rasterizer:
@@ -127,21 +130,22 @@ class Rasterizer:
     growing the frame when a scene needs more room."""
 
     def __init__(self, device: int = 0, max_n: int = 1 << 16, max_w: int = 256, max_h: int = 256,
-                 keys_per_gaussian: float = 8.0, max_keys: Optional[int] = None):
+                 keys_per_gaussian: float = 8.0, max_keys: Optional[int] = None, max_views: int = 1):
         self.device = int(device)
         self.ctx = Context.get(self.device)
         self.kpg = float(keys_per_gaussian)
         self.frame = Frame(self.ctx, max_n, max_w, max_h,
-                           max_keys or max(1024, int(max_n * self.kpg)))
+                           max_keys or max(1024, int(max_n * self.kpg * max_views)), max_views)
         self.n_keys = 0
 
-    def _ensure(self, n, w, h, keys=0):
+    def _ensure(self, n, w, h, keys=0, views=1):
         f = self.frame
-        if not f.fits(n, w, h, keys):
+        if not f.fits(n, w, h, keys, views):
             nn, ww, hh = max(n, f.max_n), max(w, f.max_w), max(h, f.max_h)
-            kk = max(keys, f.max_keys, int(nn * self.kpg))
+            vv = max(views, f.max_views)
+            kk = max(keys, f.max_keys, int(nn * self.kpg * vv))
             f.close()
-            self.frame = Frame(self.ctx, nn, ww, hh, min(kk, (1 << 31) - 1))
+            self.frame = Frame(self.ctx, nn, ww, hh, min(kk, (1 << 31) - 1), vv)
 
     def project_bin(self, g: GaussianSoA, cam, stream=None, check: bool = True):
         c = camera_struct(cam)
@@ -190,6 +194,56 @@ class Rasterizer:
         N.check(N.tg_render_bwd(self.frame.handle, g.struct(), _ptr(bg), _ptr(d_feat.contiguous()),
                                 _ptr(None if d_alpha is None else d_alpha.contiguous()), gr,
                                 _stream(stream)), "tg_render_bwd")
+        return out
+
+    # --------------------------------------------- several target views
+    def project_bin_views(self, g: GaussianSoA, cams, stream=None, check: bool = True):
+        cs = [camera_struct(c) for c in cams]
+        self._ensure(g.n, max(c.width for c in cs), max(c.height for c in cs), views=len(cs))
+        s = _stream(stream)
+        gs = g.struct()
+        for _ in range(3):
+            N.check(N.tg_project_views(self.frame.handle, gs, cs, s), "tg_project_views")
+            N.check(N.tg_bin_sort(self.frame.handle, s), "tg_bin_sort")
+            if not check:
+                return cs
+            st, nk = N.tg_frame_check(self.frame.handle)
+            self.n_keys = nk
+            if st == N.TG_OK:
+                return cs
+            if st != N.TG_ERR_CAPACITY:
+                N.check(st, "tg_frame_check")
+            self._ensure(g.n, max(c.width for c in cs), max(c.height for c in cs), int(nk * 1.25) + 1024,
+                         len(cs))
+        raise N.TgError(N.TG_ERR_CAPACITY, "binning")
+
+    def forward_views(self, g: GaussianSoA, cams, bg: Optional[torch.Tensor] = None, stream=None,
+                      check: bool = True):
+        """Render the set into every camera of `cams` together (one
+        projection, one binning, one blend launch; e.g. a stereo pair).
+        Returns a list of (feat [C, H, W], alpha [H, W])."""
+        cs = self.project_bin_views(g, cams, stream, check)
+        dev = g.mean.device
+        outs = [(torch.empty((g.c, c.height, c.width), dtype=torch.float32, device=dev),
+                 torch.empty((c.height, c.width), dtype=torch.float32, device=dev)) for c in cs]
+        N.check(N.tg_render_fwd_views(self.frame.handle, g.struct(), _ptr(bg), [_ptr(f) for f, _ in outs],
+                                      [_ptr(a) for _, a in outs], _stream(stream)), "tg_render_fwd_views")
+        self.frame.generation += 1
+        return outs
+
+    def backward_views(self, g: GaussianSoA, d_feats, d_alphas=None, bg: Optional[torch.Tensor] = None,
+                       stream=None):
+        """Gradients of the loss summed over the views of the last
+        forward_views (layout as backward)."""
+        out = empty_grads(g.n, g.c, g.mean.device)
+        gr = N.tg_grads()
+        gr.d_mean, gr.d_log_scale, gr.d_quat = _ptr(out["mean"]), _ptr(out["log_scale"]), _ptr(out["quat"])
+        gr.d_opacity_logit, gr.d_feat = _ptr(out["opacity_logit"]), _ptr(out["feat"])
+        df = [d.contiguous() for d in d_feats]
+        da = None if d_alphas is None else [None if d is None else d.contiguous() for d in d_alphas]
+        N.check(N.tg_render_bwd_views(self.frame.handle, g.struct(), _ptr(bg), [_ptr(d) for d in df],
+                                      None if da is None else [_ptr(d) for d in da], gr, _stream(stream)),
+                "tg_render_bwd_views")
         return out
 
     # -------------------------------------------------------- introspection

@@ -30,7 +30,7 @@ __all__ = [
     "Camera", "Scene", "rot_y", "rot_x", "orbit_camera", "look_at_camera",
     "make_cfg1", "make_cfg2", "make_cfg3_upstream", "make_cfg3_scaled",
     "make_cfg4_request", "make_cfg5", "make_grid_scene", "single_gaussian_scene",
-    "SourceView", "make_source_views", "make_grid_source_view",
+    "SourceView", "make_source_views", "make_grid_source_view", "stereo_pair",
 ]
 
 
@@ -406,3 +406,17 @@ def make_grid_source_view(seed: int, grid: int, n: int, c: int = 32, baseline: f
     cam = Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), fx, fx, grid / 2.0, grid / 2.0,
                  grid, grid)
     return SourceView(cam, fx * baseline / z, mask, f, np.repeat(s[:, :, None], 3, 2), o, baseline)
+
+
+def stereo_pair(cam: Camera, ipd: float = 0.064):
+    """The user's left and right eye views around a target camera (§4.2
+    renders both): the camera centre moved by -ipd/2 and +ipd/2 along the
+    camera's own x axis, same orientation and intrinsics.  With
+    x_c = R x_w + t, moving the centre by d along camera x gives
+    t' = t - (d, 0, 0)."""
+    out = []
+    for d in (-0.5 * ipd, 0.5 * ipd):
+        t = np.asarray(cam.t, np.float64) - np.array([d, 0.0, 0.0])
+        out.append(Camera(np.asarray(cam.R, np.float32).copy(), t.astype(np.float32), cam.fx, cam.fy,
+                          cam.cx, cam.cy, cam.width, cam.height, cam.znear))
+    return out
