@@ -51,6 +51,8 @@ def _load():
     lib.tgo_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
     lib.tgo_fd.argtypes = [P, P, P, P, ct.c_int64, P, ct.c_double, P, P]
     lib.tgo_zsplat.argtypes = [P, P, ct.c_int64, ct.c_double, P, P]
+    lib.tgo_normals.argtypes = [P, P, P]
+    lib.tgo_blend.argtypes = [ct.c_int, P, P, P, P, P, P, P, ct.c_double, P, P]
     lib.tgo_lift.restype = ct.c_int64
     lib.tgo_lift.argtypes = [ct.c_int, ct.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
     _lib = lib
@@ -276,3 +278,39 @@ def zsplat(mean, cam, baseline=0.0):
     dp = np.empty_like(zb)
     _load().tgo_zsplat(_p(cam_vector(cam)), _p(m), n, float(baseline), _p(zb), _p(dp))
     return zb, dp
+
+
+def normals(depth, cam):
+    """Unit normals [H, W, 3] (float32, world frame) of the depth map [H, W]
+    seen by `cam`, from central differences of the unprojected pixel
+    centres, turned toward the camera; 0 at the border and where a depth of
+    the five-point stencil is not positive."""
+    d = np.ascontiguousarray(depth, np.float32)
+    out = np.empty(d.shape + (3,), np.float32)
+    _load().tgo_normals(_p(cam_vector(cam)), _p(d), _p(out))
+    return out
+
+
+def blend(views, novel_cam, z_fused, delta):
+    """Occlusion-aware blending of source views into the novel camera (§4.3,
+    Eq. 6-10).  views: sequence of (cam, rgba [H, W, 4] uint8, depth [H, W]
+    float32, mask [H, W] uint8, normal [H, W, 3] float32).  Returns
+    (rgb [3, H, W] float32 in [0, 1], wsum [H, W] float32)."""
+    lib = _load()
+    nv = len(views)
+    keep = []
+
+    def arr(x, dt):
+        a = np.ascontiguousarray(x, dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    cams = np.concatenate([cam_vector(v[0]) for v in views]) if nv else np.zeros(19)
+    ptrs = lambda k, dt: (ct.c_void_p * max(nv, 1))(*[arr(v[k], dt) for v in views])
+    zf = np.ascontiguousarray(z_fused, np.float32)
+    H, W = zf.shape
+    rgb = np.empty((3, H, W), np.float32)
+    ws = np.empty((H, W), np.float32)
+    lib.tgo_blend(nv, _p(cams), ptrs(1, np.uint8), ptrs(2, np.float32), ptrs(3, np.uint8),
+                  ptrs(4, np.float32), _p(cam_vector(novel_cam)), _p(zf), float(delta), _p(rgb), _p(ws))
+    return rgb, ws

@@ -642,6 +642,153 @@ SplatHit splat_point(const CamF& c, const float mu[3]) {
   return h;
 }
 
+// ------------------------------------------- occlusion-aware view blending
+// §4.3 blends the source views' colours into the novel view to give the
+// high-resolution image I_blend that the refiner takes:
+//   1. the predicted depth maps are warped onto the novel view into a fused
+//      depth z_fused (the caller passes it; here it is the z-buffer splat of
+//      the lifted points into the novel camera);
+//   2. every novel pixel with a fused depth is back-projected and projected
+//      into every source view, x_i = Pi_i(Pi_novel^-1(u, v, z_fused)) (Eq. 6);
+//   3. colour c_i and depth z_i are fetched from view i by bilinear
+//      sampling at x_i's pixel coordinates (Eq. 7);
+//   4. weight w_i = M_i(x_i) Occ(x_i) cos<r(u, v), n_i> / |x_i^cam| (Eq. 8)
+//      with Occ = 1 iff |x_i.z - z_i| < delta (Eq. 9);
+//   5. I_blend = sum_i w_i c_i / sum_i w_i (Eq. 10).
+// Readings where the paper is silent:
+//   * pixel centres at (i + 0.5, j + 0.5) in every view; bilinear sampling
+//     between the four pixel centres around the point (the top-left one
+//     clamped so that all four lie inside the view), for points inside the
+//     rectangle spanned by the view's pixel centres (elsewhere the view
+//     gets no weight);
+//   * M_i(x_i) is the bilinear sample of the 0/1 mask (so it fades over one
+//     pixel at the mask's border), like every other map fetched at x_i;
+//   * the normal n_i is the unit normal of view i's depth surface (below),
+//     bilinearly sampled and renormalised, oriented toward view i's camera;
+//     the cosine is taken against the reversed ray, max(0, -<r, n_i>), so a
+//     surface facing the novel camera weighs most and one seen edge-on or
+//     from behind weighs nothing;
+//   * colours are 8-bit RGBA (alpha unused), blended as value / 255;
+//   * a pixel without a fused depth (not > 0 or infinite), or whose weights
+//     sum to zero, gets colour 0 and weight sum 0 (the refiner's mask).
+// Every step is an FP64 operation in the written order, so an IEEE
+// implementation of the same sequence reproduces the float32 outputs bit
+// for bit.
+
+// Unit normal of a depth map at pixel (i, j), in the world frame: the
+// cross product of the central differences of the camera-space points
+// P(i +- 1, j) and P(i, j +- 1) (pixel centres unprojected at their depth),
+// turned toward the camera (<n, P(i, j)> < 0).  Zero at the border and
+// where any of the five depths is not positive.
+void normal_at(const CamD& k, const float* depth, int i, int j, double out[3]) {
+  out[0] = out[1] = out[2] = 0.0;
+  if (i < 1 || j < 1 || i > k.W - 2 || j > k.H - 2) return;
+  auto z_at = [&](int a, int b) { return (double)depth[(int64_t)b * k.W + a]; };
+  const double zc = z_at(i, j), zl = z_at(i - 1, j), zr = z_at(i + 1, j), zu = z_at(i, j - 1),
+               zd = z_at(i, j + 1);
+  if (!(zc > 0.0 && zl > 0.0 && zr > 0.0 && zu > 0.0 && zd > 0.0)) return;
+  auto P = [&](int a, int b, double z, double p[3]) {
+    p[0] = ((a + 0.5) - k.cx) / k.fx * z;
+    p[1] = ((b + 0.5) - k.cy) / k.fy * z;
+    p[2] = z;
+  };
+  double pc[3], pl[3], pr[3], pu[3], pd[3];
+  P(i, j, zc, pc); P(i - 1, j, zl, pl); P(i + 1, j, zr, pr); P(i, j - 1, zu, pu); P(i, j + 1, zd, pd);
+  const double dx[3] = {pr[0] - pl[0], pr[1] - pl[1], pr[2] - pl[2]};
+  const double dy[3] = {pd[0] - pu[0], pd[1] - pu[1], pd[2] - pu[2]};
+  double c[3] = {dx[1] * dy[2] - dx[2] * dy[1], dx[2] * dy[0] - dx[0] * dy[2],
+                 PLANT(17, dx[0] * dy[1] - dx[1] * dy[0], dx[0] * dy[1] + dx[1] * dy[0])};
+  const double len = std::sqrt((c[0] * c[0] + c[1] * c[1]) + c[2] * c[2]);
+  if (!(len > 0.0)) return;
+  const double side = (c[0] * pc[0] + c[1] * pc[1]) + c[2] * pc[2];
+  const double sgn = PLANT(18, side > 0.0 ? -1.0 : 1.0, 1.0);
+  const double n[3] = {sgn * c[0] / len, sgn * c[1] / len, sgn * c[2] / len};
+  for (int a = 0; a < 3; ++a) {
+    double acc = 0.0;
+    for (int b = 0; b < 3; ++b) acc = acc + k.R[3 * b + a] * n[b];
+    out[a] = acc;
+  }
+}
+
+struct BlendView {
+  CamD cam;
+  const uint8_t* rgba;    // [H][W][4]
+  const float* depth;     // [H][W]
+  const uint8_t* mask;    // [H][W]
+  const float* normal;    // [H][W][3] world frame
+};
+
+// Colour (3) and weight sum of novel pixel (i, j) at fused depth z.
+void blend_pixel(const CamD& nv, const std::vector<BlendView>& views, int i, int j, double z, double delta,
+                 double rgb[3], double& wsum) {
+  rgb[0] = rgb[1] = rgb[2] = 0.0;
+  wsum = 0.0;
+  if (!(z > 0.0) || std::isinf(z)) return;
+  // Eq. 6: back-projection into the world
+  const double pn[3] = {((i + 0.5) - nv.cx) / nv.fx * z, ((j + 0.5) - nv.cy) / nv.fy * z, z};
+  double X[3], r[3];
+  const double pl = std::sqrt((pn[0] * pn[0] + pn[1] * pn[1]) + pn[2] * pn[2]);
+  const double rc[3] = {pn[0] / pl, pn[1] / pl, pn[2] / pl};
+  for (int a = 0; a < 3; ++a) {
+    double acc = 0.0, ra = 0.0;
+    for (int b = 0; b < 3; ++b) {
+      acc = acc + nv.R[3 * b + a] * (pn[b] - nv.t[b]);
+      ra = ra + nv.R[3 * b + a] * rc[b];
+    }
+    X[a] = acc;
+    r[a] = ra;
+  }
+  double acc[3] = {0.0, 0.0, 0.0}, ws = 0.0;
+  for (const BlendView& v : views) {
+    const CamD& k = v.cam;
+    double xc[3];
+    for (int a = 0; a < 3; ++a) xc[a] = ((k.R[3 * a] * X[0] + k.R[3 * a + 1] * X[1]) + k.R[3 * a + 2] * X[2]) + k.t[a];
+    if (!(xc[2] > k.znear)) continue;
+    const double u = (k.fx * xc[0]) / xc[2] + k.cx, w = (k.fy * xc[1]) / xc[2] + k.cy;
+    // Eq. 7: bilinear taps around (u, w) between pixel centres; (su, sw)
+    // must lie in the rectangle spanned by the view's pixel centres
+    const double su = u - PLANT(19, 0.5, 0.0), sw = w - 0.5;
+    if (!(su >= 0.0 && su <= k.W - 1.0 && sw >= 0.0 && sw <= k.H - 1.0)) continue;
+    const double fu = std::min(std::floor(su), std::max(k.W - 2.0, 0.0));
+    const double fw = std::min(std::floor(sw), std::max(k.H - 2.0, 0.0));
+    const int i0 = (int)fu, j0 = (int)fw;
+    const int i1 = std::min(i0 + 1, k.W - 1), j1 = std::min(j0 + 1, k.H - 1);
+    const double a = su - fu, b = sw - fw;
+    const double w00 = (1.0 - a) * (1.0 - b), w10 = a * (1.0 - b), w01 = (1.0 - a) * b, w11 = a * b;
+    const int64_t p00 = (int64_t)j0 * k.W + i0, p10 = (int64_t)j0 * k.W + i1, p01 = (int64_t)j1 * k.W + i0,
+                  p11 = (int64_t)j1 * k.W + i1;
+    auto interp = [&](double f00, double f10, double f01, double f11) {
+      return ((w00 * f00 + w10 * f10) + w01 * f01) + w11 * f11;
+    };
+    const double m = interp(v.mask[p00] ? 1.0 : 0.0, v.mask[p10] ? 1.0 : 0.0, v.mask[p01] ? 1.0 : 0.0,
+                            v.mask[p11] ? 1.0 : 0.0);
+    if (!(m > 0.0)) continue;
+    const double zi = interp(v.depth[p00], v.depth[p10], v.depth[p01], v.depth[p11]);
+    // Eq. 9: the occlusion check against the view's own depth
+    if (!(std::fabs(xc[2] - zi) < delta)) continue;
+    double n[3];
+    for (int q = 0; q < 3; ++q)
+      n[q] = interp(v.normal[3 * p00 + q], v.normal[3 * p10 + q], v.normal[3 * p01 + q], v.normal[3 * p11 + q]);
+    const double nl = std::sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
+    if (!(nl > 0.0)) continue;
+    const double cosv = PLANT(20, -((r[0] * n[0] + r[1] * n[1]) + r[2] * n[2]) / nl,
+                              ((r[0] * n[0] + r[1] * n[1]) + r[2] * n[2]) / nl);
+    if (!(cosv > 0.0)) continue;
+    const double dist = std::sqrt((xc[0] * xc[0] + xc[1] * xc[1]) + xc[2] * xc[2]);
+    // Eq. 8
+    const double wt = (m * cosv) / PLANT(21, dist, 1.0);
+    for (int q = 0; q < 3; ++q) {
+      const double c = interp(v.rgba[4 * p00 + q], v.rgba[4 * p10 + q], v.rgba[4 * p01 + q], v.rgba[4 * p11 + q]) / 255.0;
+      acc[q] = acc[q] + wt * c;
+    }
+    ws = ws + wt;
+  }
+  if (!(ws > 0.0)) return;
+  // Eq. 10
+  for (int q = 0; q < 3; ++q) rgb[q] = acc[q] / ws;
+  wsum = ws;
+}
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -1087,6 +1234,45 @@ void tgo_zsplat(const double* cam, const double* mean, int64_t n, double baselin
   if (disp)
     for (int64_t p = 0; p < P; ++p)
       disp[p] = std::isinf(zbuf[p]) ? 0.0f : (float)((double)c.fx * (double)(float)baseline / (double)zbuf[p]);
+}
+
+// Normal map [H][W][3] (float32, world frame) of a depth map [H][W] seen
+// by the camera `cam` (camera vector of tgo_create); see normal_at.
+void tgo_normals(const double* cam, const float* depth, float* normal) {
+  const CamD k = cam_from(cam);
+  for (int j = 0; j < k.H; ++j)
+    for (int i = 0; i < k.W; ++i) {
+      double n[3];
+      normal_at(k, depth, i, j, n);
+      for (int a = 0; a < 3; ++a) normal[3 * ((int64_t)j * k.W + i) + a] = (float)n[a];
+    }
+}
+
+// Occlusion-aware blending of n_views source views into the novel camera
+// `novel` (camera vectors as tgo_create; per view cams[19 v ..], rgba[v]
+// [H][W][4] uint8, depth[v] [H][W], mask[v] [H][W], normal[v] [H][W][3]),
+// given z_fused [H_n][W_n]: rgb [3][H_n][W_n] and wsum [H_n][W_n] (float32).
+void tgo_blend(int n_views, const double* cams, const uint8_t* const* rgba, const float* const* depth,
+               const uint8_t* const* mask, const float* const* normal, const double* novel, const float* z_fused,
+               double delta, float* rgb, float* wsum) {
+  std::vector<BlendView> views((size_t)n_views);
+  for (int v = 0; v < n_views; ++v) {
+    views[v].cam = cam_from(cams + 19 * v);
+    views[v].rgba = rgba[v];
+    views[v].depth = depth[v];
+    views[v].mask = mask[v];
+    views[v].normal = normal[v];
+  }
+  const CamD nv = cam_from(novel);
+  const int64_t P = (int64_t)nv.W * nv.H;
+  for (int j = 0; j < nv.H; ++j)
+    for (int i = 0; i < nv.W; ++i) {
+      const int64_t p = (int64_t)j * nv.W + i;
+      double c[3], ws;
+      blend_pixel(nv, views, i, j, (double)z_fused[p], delta, c, ws);
+      for (int q = 0; q < 3; ++q) rgb[q * P + p] = (float)c[q];
+      wsum[p] = (float)ws;
+    }
 }
 
 }  // extern "C"

@@ -31,6 +31,11 @@ MUTANTS = {
     14: "lifting: camera rotation not transposed",
     15: "z-buffer: a point lands in the pixel whose centre is nearest",
     16: "z-buffer: the last point wins instead of the nearest",
+    17: "normals: sign of one cross-product term",
+    18: "normals: not turned toward the camera",
+    19: "blending: bilinear taps around the pixel corner",
+    20: "blending: cosine against the ray instead of the reversed ray",
+    21: "blending: weight without the distance term",
 }
 
 
@@ -45,6 +50,7 @@ def test_pins_catch_planted_mistake(plant, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_lift_pins.py"),
                         os.path.join(ROOT, "tests", "test_zsplat_pins.py"),
+                        os.path.join(ROOT, "tests", "test_blend_pins.py"),
                         "-k", "not fd_cfg3_small"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {plant} ({MUTANTS[plant]}) survived the pins:\n{r.stdout[-2000:]}"
