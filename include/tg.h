@@ -351,6 +351,55 @@ tg_status tg_zsplat(tg_ctx* ctx, const float* mean, int64_t n, const tg_camera* 
                     const float* baselines /* host */, int32_t n_views, float* zbuf, float* disparity,
                     void* stream);
 
+/* ------------------------------------- occlusion-aware view blending
+ * §4.3 gives the refiner a high-resolution image I_blend blended from the
+ * source views (Eq. 6-10).  Per novel pixel (u, v) with fused depth z (the
+ * source depth maps warped onto the novel view, for instance with
+ * tg_zsplat of their lifted points): back-project the pixel centre to the
+ * world point X (Eq. 6), project X into every source view, fetch colour,
+ * depth, mask and normal there by bilinear sampling (Eq. 7), weigh view i
+ * by w_i = M_i * Occ_i * max(0, -<r, n_i>) / |x_i^cam| (Eq. 8) with
+ * Occ_i = 1 iff |x_i.z - z_i| < delta (Eq. 9), r the unit ray of the novel
+ * pixel and n_i the sampled normal renormalised, and average the colours
+ * with these weights (Eq. 10).  Readings where the paper is silent:
+ * bilinear sampling between the four pixel centres around the point (the
+ * top-left one clamped so all four lie in the view), only inside the
+ * rectangle spanned by the view's pixel centres; the 0/1 mask is sampled
+ * like the other maps; colours are 8-bit over 255.  Every quantity is FP64
+ * in a fixed operation order, so the float32 outputs are reproducible bit
+ * for bit. */
+
+#define TG_BLEND_MAX_VIEWS 8
+
+/* One source view of the blending (host struct of device pointers):
+ *   rgba   [H][W][4] uint8 colour (alpha unused), 4-byte aligned
+ *   depth  [H][W] float32 depth in metres (the view's predicted depth)
+ *   mask   [H][W] uint8, M_i: non-zero where the view's pixels are valid
+ *   normal [H][W][3] float32 world-frame unit normals (tg_depth_normals) */
+typedef struct tg_blend_view {
+  tg_camera cam;
+  const uint8_t* rgba;
+  const float* depth;
+  const uint8_t* mask;
+  const float* normal;
+} tg_blend_view;
+
+/* Unit normals [H][W][3] (world frame) of a depth map [H][W] seen by cam:
+ * the cross product of the central differences of the unprojected pixel
+ * centres P(i +- 1, j), P(i, j +- 1), turned toward the camera; 0 on the
+ * border and where a depth of the five-point stencil is not positive. */
+tg_status tg_depth_normals(tg_ctx* ctx, const tg_camera* cam /* host */, const float* depth, float* normal,
+                           void* stream);
+
+/* Blend n_views (0..TG_BLEND_MAX_VIEWS) source views (host array) into the
+ * novel camera (host): z_fused [H][W] float32 (pixels whose depth is not
+ * positive or infinite get nothing), delta > 0 in metres.  Outputs:
+ * out_rgb [3][H][W] float32 in [0, 1] and out_wsum [H][W] float32, the sum
+ * of the weights (0 where no view contributes; the colour is then 0). */
+tg_status tg_blend_views(tg_ctx* ctx, const tg_blend_view* views /* host */, int32_t n_views,
+                         const tg_camera* novel /* host */, const float* z_fused, float delta, float* out_rgb,
+                         float* out_wsum, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request loop that renders many target views at once (the system of §5.3
  * renders every frame of every terminal through R_G, under CUDA Graphs).

@@ -32,7 +32,7 @@ EXPORTS = [
     "tg_serve_poll", "tg_serve_wait", "tg_serve_release", "tg_serve_destroy",
     "tg_render_noalloc", "tg_lifter_create", "tg_lifter_destroy", "tg_lift",
     "tg_zsplat", "tg_frame_create_views", "tg_project_views", "tg_render_fwd_views",
-    "tg_render_bwd_views",
+    "tg_render_bwd_views", "tg_depth_normals", "tg_blend_views",
 ]
 
 # limits of tg_render_noalloc (include/tg.h)
@@ -83,6 +83,7 @@ class tg_result(ct.Structure):
 
 TG_LIFT_MAX_VIEWS = 8
 TG_MAX_VIEWS = 8
+TG_BLEND_MAX_VIEWS = 8
 TG_ZSPLAT_MAX_VIEWS = 8
 
 
@@ -95,6 +96,11 @@ class tg_source_view(ct.Structure):
 class tg_gaussian_buffers(ct.Structure):
     _fields_ = [("mean", ct.c_void_p), ("scale", ct.c_void_p), ("quat", ct.c_void_p),
                 ("opacity", ct.c_void_p), ("feat", ct.c_void_p), ("cap", ct.c_int64)]
+
+
+class tg_blend_view(ct.Structure):
+    _fields_ = [("cam", tg_camera), ("rgba", ct.c_void_p), ("depth", ct.c_void_p), ("mask", ct.c_void_p),
+                ("normal", ct.c_void_p)]
 
 
 class TgError(RuntimeError):
@@ -173,6 +179,10 @@ def lib():
     L.tg_render_bwd_views.restype = I
     L.tg_render_bwd_views.argtypes = [P, ct.POINTER(tg_gaussians), P, ct.POINTER(P), ct.POINTER(P),
                                       ct.POINTER(tg_grads), P]
+    L.tg_depth_normals.restype = I
+    L.tg_depth_normals.argtypes = [P, ct.POINTER(tg_camera), P, P, P]
+    L.tg_blend_views.restype = I
+    L.tg_blend_views.argtypes = [P, ct.POINTER(tg_blend_view), I32, ct.POINTER(tg_camera), P, ct.c_float, P, P, P]
     _lib = L
     return L
 
@@ -343,3 +353,14 @@ def tg_render_fwd_views(frame: int, g: tg_gaussians, bg: int, out_feat, out_alph
 def tg_render_bwd_views(frame: int, g: tg_gaussians, bg: int, d_feat, d_alpha, grads: tg_grads, stream: int) -> int:
     return lib().tg_render_bwd_views(frame, ct.byref(g), bg, _ptr_array(d_feat), _ptr_array(d_alpha),
                                      ct.byref(grads), stream)
+
+
+def tg_depth_normals(ctx: int, cam: tg_camera, depth: int, normal: int, stream: int) -> int:
+    return lib().tg_depth_normals(ctx, ct.byref(cam), depth, normal, stream)
+
+
+def tg_blend_views(ctx: int, views, novel: tg_camera, z_fused: int, delta: float, out_rgb: int, out_wsum: int,
+                   stream: int) -> int:
+    arr = (tg_blend_view * max(1, len(views)))(*views)
+    return lib().tg_blend_views(ctx, arr, len(views), ct.byref(novel), z_fused, float(delta), out_rgb, out_wsum,
+                                stream)

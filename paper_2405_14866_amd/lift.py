@@ -11,7 +11,7 @@ import torch
 from . import _native as N
 from .rasterize import Context, GaussianSoA, _ptr, _stream, camera_struct
 
-__all__ = ["SourceViewMaps", "GaussianBuffers", "Lifter", "zsplat"]
+__all__ = ["SourceViewMaps", "GaussianBuffers", "Lifter", "zsplat", "depth_normals", "blend_views"]
 
 
 class SourceViewMaps:
@@ -127,3 +127,32 @@ def zsplat(mean: torch.Tensor, cams, baselines=None, with_disparity: bool = True
         out.append((zb[o:o + h * w].view(h, w), None if dp is None else dp[o:o + h * w].view(h, w)))
         o += h * w
     return out
+
+
+def depth_normals(depth: torch.Tensor, cam, stream=None) -> torch.Tensor:
+    """tg_depth_normals: unit normals [H, W, 3] (world frame) of a depth map
+    [H, W] (float32, device) seen by `cam`."""
+    ctx = Context.get(depth.device.index or 0)
+    out = torch.empty(tuple(depth.shape) + (3,), dtype=torch.float32, device=depth.device)
+    N.check(N.tg_depth_normals(ctx.handle, camera_struct(cam), _ptr(depth.contiguous()), _ptr(out),
+                               _stream(stream)), "tg_depth_normals")
+    return out
+
+
+def blend_views(views, novel_cam, z_fused: torch.Tensor, delta: float, stream=None):
+    """tg_blend_views: occlusion-aware blending (§4.3).  views: sequence of
+    (cam, rgba [H, W, 4] uint8, depth [H, W], mask [H, W] uint8, normal
+    [H, W, 3]) device tensors.  Returns (rgb [3, H, W], wsum [H, W])."""
+    ctx = Context.get(z_fused.device.index or 0)
+    H, W = int(z_fused.shape[0]), int(z_fused.shape[1])
+    rgb = torch.empty((3, H, W), dtype=torch.float32, device=z_fused.device)
+    ws = torch.empty((H, W), dtype=torch.float32, device=z_fused.device)
+    st = []
+    for cam, rgba, depth, mask, normal in views:
+        v = N.tg_blend_view()
+        v.cam = camera_struct(cam)
+        v.rgba, v.depth, v.mask, v.normal = _ptr(rgba), _ptr(depth), _ptr(mask), _ptr(normal)
+        st.append(v)
+    N.check(N.tg_blend_views(ctx.handle, st, camera_struct(novel_cam), _ptr(z_fused.contiguous()), delta,
+                             _ptr(rgb), _ptr(ws), _stream(stream)), "tg_blend_views")
+    return rgb, ws

@@ -30,7 +30,8 @@ __all__ = [
     "Camera", "Scene", "rot_y", "rot_x", "orbit_camera", "look_at_camera",
     "make_cfg1", "make_cfg2", "make_cfg3_upstream", "make_cfg3_scaled",
     "make_cfg4_request", "make_cfg5", "make_grid_scene", "single_gaussian_scene",
-    "SourceView", "make_source_views", "make_grid_source_view", "stereo_pair",
+    "SourceView", "make_source_views", "make_grid_source_view", "stereo_pair", "source_rgba",
+    "source_depth",
 ]
 
 
@@ -420,3 +421,27 @@ def stereo_pair(cam: Camera, ipd: float = 0.064):
         out.append(Camera(np.asarray(cam.R, np.float32).copy(), t.astype(np.float32), cam.fx, cam.fy,
                           cam.cx, cam.cy, cam.width, cam.height, cam.znear))
     return out
+
+
+def source_rgba(view: SourceView, seed: int) -> np.ndarray:
+    """A seeded 8-bit RGBA image [H, W, 4] for a source view (the stand-in
+    for the captured colour frame): smooth colour bands over the image plus
+    per-pixel noise, alpha 255."""
+    rng = np.random.default_rng(seed)
+    H, W = view.mask.shape
+    j, i = np.mgrid[0:H, 0:W].astype(np.float64)
+    ph = rng.uniform(0, 2 * np.pi, 3)
+    img = np.zeros((H, W, 4), np.uint8)
+    for q in range(3):
+        band = 128.0 + 90.0 * np.sin(2 * np.pi * (i / W * (q + 1.5)) + ph[q]) * np.cos(2 * np.pi * j / H * 1.3)
+        img[..., q] = np.clip(band + rng.normal(0.0, 12.0, (H, W)), 0, 255).astype(np.uint8)
+    img[..., 3] = 255
+    return img
+
+
+def source_depth(view: SourceView) -> np.ndarray:
+    """The view's depth map [H, W] float32 from its disparity (fx B / d, 0
+    where the disparity is not positive)."""
+    d = view.disparity.astype(np.float64)
+    z = np.where(d > 0, view.cam.fx * view.baseline / np.where(d > 0, d, 1.0), 0.0)
+    return z.astype(np.float32)
