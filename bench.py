@@ -8,7 +8,15 @@ hot path over one frame with the inputs resident in HBM:
 tg_project -> tg_bin_sort -> tg_render_fwd.
 
 Prints one JSON line (frames/s, p50/p99 ms per frame, per-kernel times, the
-roofline of the dominant kernel and the FP64 oracle's CPU rate beside it).
+roofline of the dominant kernel and of every other kernel against its own
+bound, the FP64 oracle's CPU rate beside it), plus the legs of the rest of
+the workload: the adjoint, the serving loop (closed loop, Poisson arrivals
+at the paper's 240 frames/s and an offered-load sweep), the serving
+workload's own request mix with every request's Gaussians lifted on the
+device, the full-resolution stress frames (forward + adjoint of four frames
+in one batch, with and without reuse of the sort), the stereo pair, and the
+steps around the rasterizer (lifting, z-buffer splat, normals, view
+blending).
 """
 import argparse
 import json
@@ -35,7 +43,12 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (scale for HBM counters)")
     p.add_argument("--streams", type=int, default=8, help="serving: client streams")
-    p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving legs")
+    p.add_argument("--no-stress", action="store_true", help="skip the full-resolution stress leg")
+    p.add_argument("--no-upstream", action="store_true",
+                   help="skip the lifting / z-buffer / blending legs")
+    p.add_argument("--serve-frames", type=int, default=4000,
+                   help="closed-loop serving: completed frames timed (at least --steps)")
     return p.parse_args()
 
 
@@ -92,6 +105,16 @@ def pct(xs, q):
     return xs[k]
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, budget_s):
     """The FP64 oracle (projection, tile lists, per-pixel blend) on the
     host's cores, frames of the same workload repeated until the budget."""
@@ -108,7 +131,7 @@ def cpu_baseline(scene, budget_s):
         if time.perf_counter() - t_all > budget_s or len(times) >= 50:
             break
     per = sum(times) / len(times)
-    return {"value": 1.0 / per, "unit": "frames/s", "cores": threads, "kind": "oracle",
+    return {"value": 1.0 / per, "unit": "frames/s", "cores": threads, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{len(times)} full frames of the same workload (FP64 oracle: "
                       f"float32 binning spec + tile lists + per-pixel blend), "
                       f"{per * 1e3:.0f} ms each"}
@@ -164,117 +187,233 @@ def serve_leg(scene, g, streams, frames, warmup, torch, rate=240.0, open_frames=
             submitted += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # open loop at the paper's frame rate
-    import numpy as np
-    rng = np.random.default_rng(4)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, open_frames))
-    pending, olat, obatch = [], [], []
-    t1 = time.perf_counter()
-    for j, ta in enumerate(arrivals):
-        while time.perf_counter() - t1 < ta:     # retire finished requests until the arrival
-            if pending and srv.poll(pending[0][1]).status != 1:     # 1: still pending
-                r = srv.wait(pending.pop(0)[1])
-                assert r.status == 0, r.status
-                olat.append(r.latency_ms)
-                obatch.append(r.batch_size)
-            else:
-                time.sleep(20e-6)
-        i = j % streams
-        pending.append((i, srv.submit(per_stream[i], scene.cam, *outs[i][j % depth], stream_id=i)))
-    for _, t in pending:
-        r = srv.wait(t)
-        assert r.status == 0, r.status
-        olat.append(r.latency_ms)
-        obatch.append(r.batch_size)
+    # open loop at the paper's frame rate, then an offered-load sweep up to saturation;
+    # output buffers come from a pool (beyond saturation the queue outgrows it and
+    # renders may share an output buffer: their images are not read)
+    pool = [(torch.empty((c, H, W), device="cuda"), torch.empty((H, W), device="cuda")) for _ in range(64)]
+    submit_k = lambda j: srv.submit(per_stream[j % streams], scene.cam, *pool[j % len(pool)],
+                                    stream_id=j % streams)
+    olat, obatch, _ = open_loop(srv, submit_k, rate, open_frames, seed=4)
+    sweep = []
+    for r in (240.0, 960.0, 1920.0, 2880.0, 3840.0, 4800.0, 6000.0):
+        count = int(max(240, min(4000, r * 0.6)))
+        lat_r, b_r, span = open_loop(srv, submit_k, r, count, seed=int(r))
+        achieved = len(lat_r) / span
+        sweep.append({"offered_per_s": r, "achieved_per_s": round(achieved, 1), "requests": len(lat_r),
+                      "p50_ms": round(pct(lat_r, 50), 4), "p99_ms": round(pct(lat_r, 99), 4),
+                      "mean_batch": round(sum(b_r) / len(b_r), 2)})
+        if achieved < 0.9 * r:          # saturated: completions no longer keep up with arrivals
+            break
     srv.close()
     return {"frames_per_s": round(done / wall, 2), "closed_loop_p50_ms": round(pct(lat, 50), 4),
             "closed_loop_p99_ms": round(pct(lat, 99), 4), "frames": done, "streams": streams,
             "mean_batch": round(sum(batch_sizes) / len(batch_sizes), 2), "graph": True,
             "open_loop": {"rate_per_s": rate, "requests": len(olat), "p50_ms": round(pct(olat, 50), 4),
                           "p99_ms": round(pct(olat, 99), 4),
-                          "mean_batch": round(sum(obatch) / len(obatch), 2)}}
+                          "mean_batch": round(sum(obatch) / len(obatch), 2)},
+            "load_sweep": sweep}
 
 
-def mixed_serving_leg(torch, streams=8, requests=2000, rate=240.0, closed=400):
-    """The serving workload itself: stream s keeps one Gaussian set resident
-    (N ~ U{100k..1M} from the small-scene generator, C = 32); request k comes
-    from stream k mod `streams` with its own target (512^2 / 768^2 / 1024^2,
-    yaw +-10 deg, pitch +-5 deg).  Open loop: `requests` Poisson arrivals at
-    `rate` per second, latency submit -> observed completion.  Closed loop:
-    two requests in flight per stream until `closed` complete."""
+def open_loop(srv, submit, rate, count, seed):
+    """`count` requests arriving as a Poisson process of `rate` per second;
+    submit(j) queues request j.  Returns (latencies ms, batch sizes, span s
+    from the first arrival to the last completion)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+    pending, lat, bsz = [], [], []
+    t1 = time.perf_counter()
+    for j, ta in enumerate(arrivals):
+        while time.perf_counter() - t1 < ta:     # retire finished requests until the arrival
+            if pending and srv.poll(pending[0]).status != 1:     # 1: still pending
+                r = srv.wait(pending.pop(0))
+                assert r.status == 0, r.status
+                lat.append(r.latency_ms)
+                bsz.append(r.batch_size)
+            else:
+                time.sleep(20e-6)
+        pending.append(submit(j))
+    for t in pending:
+        r = srv.wait(t)
+        assert r.status == 0, r.status
+        lat.append(r.latency_ms)
+        bsz.append(r.batch_size)
+    span = time.perf_counter() - t1 - float(arrivals[0])
+    return lat, bsz, span
+
+
+def mixed_serving_leg(torch, streams=8, requests=2000, rate=240.0, closed=400, grid=1000):
+    """The serving workload itself, every request bringing its own Gaussian
+    set produced on the device.  Stream s keeps its source maps resident (a
+    grid x grid view of the small-scene generator: depth U[1, 2] m, scale
+    jitter lognormal(0, 0.2), opacity U[0.05, 0.95], C = 32 encoder features
+    N(0, 1)) and the server keeps a Gaussian arena per stream.  Request k
+    comes from stream k mod `streams` with its own count N ~ U{100k..1M} and
+    target (512^2 / 768^2 / 1024^2, yaw +-10 deg, pitch +-5 deg); before its
+    arrival its set is made on a producer stream: the first N pixels of a
+    ceil(sqrt N)-square view (fx = side, principal point at the centre)
+    marked in the mask and the scale map depth / side x jitter (torch
+    element-wise ops standing in for the matting network and the encoder's
+    scale head), then tg_lift into the stream's arena.  Open loop: `requests`
+    Poisson arrivals at `rate` per second, latency submit -> observed
+    completion (the lifting happens before the arrival).  Closed loop: two
+    arenas per stream, two requests in flight per stream, each new request
+    lifted into the arena its predecessor on it released, until `closed`
+    complete (lifting included in the wall time)."""
+    import math
     import numpy as np
     import scenes
-    from paper_2405_14866_amd.rasterize import GaussianSoA
+    from paper_2405_14866_amd import _native as N
+    from paper_2405_14866_amd.lift import Lifter
+    from paper_2405_14866_amd.rasterize import _ptr, camera_struct
     from paper_2405_14866_amd.serve import Server
-    scs = [scenes.make_cfg4_request(i) for i in range(streams)]
-    gs = [GaussianSoA.from_scene(sc) for sc in scs]
-    c = 32
-    side = 1024
-    bufs = [[torch.empty(c * side * side, device="cuda") for _ in range(2)] for _ in range(streams)]
-    abufs = [[torch.empty(side * side, device="cuda") for _ in range(2)] for _ in range(streams)]
-    cams = [scenes.serving_camera(k) for k in range(max(requests, closed))]
-    n_max = max(sc.n for sc in scs)
-    batch = 8
-    srv = Server(0, c=c, slots=3, max_batch=batch, max_gauss_per_batch=batch * n_max + 8192,
-                 max_keys_per_batch=int(batch * n_max * 4.5), max_pixels_per_batch=batch * side * side,
+    c, side = 32, 1024
+    P = grid * grid
+    rng = np.random.default_rng(40000)
+    maps = []
+    for s_ in range(streams):
+        r = np.random.default_rng(40100 + s_)
+        f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device="cuda")
+        maps.append(dict(z=f32(r.uniform(1.0, 2.0, P)), jit=f32(np.exp(0.2 * r.standard_normal(P))),
+                         op=f32(r.uniform(0.05, 0.95, P)), feat=f32(r.standard_normal((P, c))),
+                         scale=torch.empty(3 * P, device="cuda"),
+                         mask=torch.zeros(P, dtype=torch.uint8, device="cuda")))
+    n_req = 2 * streams + closed + requests
+    ns = rng.integers(100_000, 1_000_001, n_req)
+    cams = [scenes.serving_camera(k) for k in range(n_req)]
+    srv = Server(0, c=c, slots=3, max_batch=8, max_gauss_per_batch=8 * 1_000_000 + 8192,
+                 max_keys_per_batch=int(8 * 1_000_000 * 4.5), max_pixels_per_batch=8 * side * side,
                  max_side=side, use_graph=True, keys_per_gaussian=4.5)
+    arenas = {sid: srv.stream_arena(sid, 1_000_000) for sid in range(2 * streams)}
+    bufs = {sid: (torch.empty(c * side * side, device="cuda"), torch.empty(side * side, device="cuda"))
+            for sid in range(2 * streams)}
+    lifter = Lifter(0, max_pixels=P)
+    prod = torch.cuda.Stream(0)
+    n_host = torch.zeros(1, dtype=torch.int64, pin_memory=True)
+    lift_ms = []
 
-    def submit(k, slot):
-        i = k % streams
+    def produce(k, sid):
+        """Make request k's set in arena `sid`; returns its Gaussian count."""
+        m = maps[k % streams]
+        nk = int(ns[k])
+        g = int(math.ceil(math.sqrt(nk)))
+        t0 = time.perf_counter()
+        with torch.cuda.stream(prod):
+            m["mask"][:g * g] = (torch.arange(g * g, device="cuda") < nk).to(torch.uint8)
+            m["scale"].view(P, 3)[:g * g] = (m["z"][:g * g] / g * m["jit"][:g * g])[:, None]
+        v = N.tg_source_view()
+        v.cam = camera_struct(dict(R=np.eye(3), t=np.zeros(3), fx=g, fy=g, cx=g / 2.0, cy=g / 2.0, width=g,
+                                   height=g))
+        v.disparity, v.depth = None, _ptr(m["z"])
+        v.mask, v.feat, v.scale, v.opacity = _ptr(m["mask"]), _ptr(m["feat"]), _ptr(m["scale"]), _ptr(m["op"])
+        v.baseline = 0.0
+        a = arenas[sid]
+        out = N.tg_gaussian_buffers()
+        out.mean, out.scale, out.quat, out.opacity, out.feat = a.mean, a.scale, a.quat, a.opacity, a.feat
+        out.cap = 1_000_000
+        N.check(N.tg_lift(lifter.handle, [v], c, out, _ptr(lifter.n_out), int(prod.cuda_stream)), "tg_lift")
+        with torch.cuda.stream(prod):
+            n_host.copy_(lifter.n_out, non_blocking=True)
+        prod.synchronize()
+        lift_ms.append((time.perf_counter() - t0) * 1e3)
+        n = int(n_host.item())
+        assert n == nk, (n, nk)
+        return n
+
+    def submit(k, sid, n):
         cam = cams[k]
         h, w = cam.height, cam.width
-        f = bufs[i][slot][:c * h * w].view(c, h, w)
-        a = abufs[i][slot][:h * w].view(h, w)
-        return srv.submit(gs[i], cam, f, a, stream_id=i)
+        f = bufs[sid][0][:c * h * w].view(c, h, w)
+        a = bufs[sid][1][:h * w].view(h, w)
+        return srv.submit(arenas[sid], cam, f, a, stream_id=sid, n=n)
 
     for k in range(2 * streams):                        # warm-up
-        srv.wait(submit(k, 0))
+        sid = k % streams
+        srv.wait(submit(k, sid, produce(k, sid)))
     torch.cuda.synchronize()
-    # closed loop
+    # closed loop: client i alternates between arenas i and streams + i
+    base = 2 * streams
     t0 = time.perf_counter()
     inflight, submitted, done, clat = [], 0, 0, []
-    for k in range(min(2 * streams, closed)):
-        inflight.append(submit(k, k // streams))
+    for j in range(min(2 * streams, closed)):
+        sid = (j % streams) + streams * (j // streams)
+        inflight.append((sid, submit(base + j, sid, produce(base + j, sid))))
         submitted += 1
     while inflight:
-        t = inflight.pop(0)
+        sid, t = inflight.pop(0)
         r = srv.wait(t)
         assert r.status == 0, r.status
         clat.append(r.latency_ms)
         done += 1
         if submitted < closed:
-            inflight.append(submit(submitted, (submitted // streams) % 2))
+            k = base + submitted
+            inflight.append((sid, submit(k, sid, produce(k, sid))))
             submitted += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # open loop
-    rng = np.random.default_rng(5)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, requests))
-    pending, olat, obatch = [], [], []
+    lift_closed = list(lift_ms)
+    lift_ms.clear()
+    # open loop: a producer thread lifts every request's set ahead of its
+    # arrival, into its stream's arena once that stream's previous request
+    # (`streams` requests earlier) has been retired; the main thread submits
+    # each request at its arrival time and retires finished ones
+    import threading
+    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / rate, requests))
+    k0 = base + closed
+    ready = [threading.Event() for _ in range(requests)]
+    retired = [threading.Event() for _ in range(requests)]
+    n_of, t_ready = [0] * requests, [0.0] * requests
     t1 = time.perf_counter()
-    for k, ta in enumerate(arrivals):
-        while time.perf_counter() - t1 < ta:
-            if pending and srv.poll(pending[0]).status != 1:
-                r = srv.wait(pending.pop(0))
-                assert r.status == 0, r.status
-                olat.append(r.latency_ms)
-                obatch.append(r.batch_size)
-            else:
-                time.sleep(20e-6)
-        # a stream's two output buffers alternate; its previous request on a
-        # buffer has long finished at 30 requests/s per stream
-        pending.append(submit(k, (k // streams) % 2))
-    for t in pending:
+
+    def producer():
+        for k in range(requests):
+            if k >= streams:
+                retired[k - streams].wait()
+            n_of[k] = produce(k0 + k, k % streams)
+            t_ready[k] = time.perf_counter() - t1
+            ready[k].set()
+
+    th = threading.Thread(target=producer, daemon=True)
+    th.start()
+    pending, olat, obatch = [], [], []
+
+    def collect(idx, t):
         r = srv.wait(t)
         assert r.status == 0, r.status
         olat.append(r.latency_ms)
         obatch.append(r.batch_size)
+        retired[idx].set()
+
+    for j, ta in enumerate(arrivals):
+        while time.perf_counter() - t1 < ta:
+            if pending and srv.poll(pending[0][1]).status != 1:
+                collect(*pending.pop(0))
+            else:
+                time.sleep(20e-6)
+        while not ready[j].is_set():           # (the producer may wait for a retirement)
+            if pending and srv.poll(pending[0][1]).status != 1:
+                collect(*pending.pop(0))
+            else:
+                time.sleep(20e-6)
+        pending.append((j, submit(k0 + j, j % streams, n_of[j])))
+    for idx, t in pending:
+        collect(idx, t)
+    th.join()
+    early = sum(1 for j in range(requests) if t_ready[j] <= arrivals[j])
     srv.close()
-    pct = lambda xs, q: float(np.percentile(xs, q))
-    return {"requests": len(olat), "rate_per_s": rate, "p50_ms": round(pct(olat, 50), 4),
-            "p99_ms": round(pct(olat, 99), 4), "mean_batch": round(float(np.mean(obatch)), 2),
+    lifter.close()
+    q = lambda xs, p_: float(np.percentile(xs, p_))
+    return {"requests": len(olat), "rate_per_s": rate, "p50_ms": round(q(olat, 50), 4),
+            "p99_ms": round(q(olat, 99), 4), "mean_batch": round(float(np.mean(obatch)), 2),
             "closed_loop_frames_per_s": round(done / wall, 2), "closed_loop_requests": done,
-            "n_per_stream": [sc.n for sc in scs], "streams": streams}
+            "closed_loop_p99_ms": round(q(clat, 99), 4),
+            "gaussians_per_request": {"min": int(ns.min()), "mean": int(ns.mean()), "max": int(ns.max())},
+            "lift_on_device": {"where": "tg_lift into the stream's arena before the arrival",
+                               "open_loop_produce_ms_p50": round(q(lift_ms, 50), 4),
+                               "open_loop_produce_ms_p99": round(q(lift_ms, 99), 4),
+                               "closed_loop_produce_ms_p50": round(q(lift_closed, 50), 4),
+                               "ready_before_arrival": int(early)},
+            "streams": streams}
 
 
 def backward_leg(fr, gs, scene, s, steps, warmup, fwd_step, torch):
@@ -313,6 +452,233 @@ def backward_leg(fr, gs, scene, s, steps, warmup, fwd_step, torch):
     return {"backward_ms": round(sum(b_ms) / k, 4), "backward_p99_ms": round(pct(b_ms, 99), 4),
             "train_step_ms": round(sum(t_ms) / k, 4), "reps": k, "grads_finite": finite,
             "upstream": "dL/dF ~ N(0,1) [C,H,W], dL/dalpha = 0"}
+
+
+def roof(name, bound, amount, seconds, unit_amount, note):
+    """A kernel against its own bound: amount (bytes or flops per launch)
+    over the measured seconds per launch."""
+    if bound == "hbm":
+        achieved = amount / seconds / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "bytes_per_launch": int(amount),
+                "us_per_launch": round(seconds * 1e6, 2), "algorithmic": note}
+    achieved = amount / seconds / 1e12
+    return {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": unit_amount,
+            "unit": "TFLOP/s", "frac": round(achieved / unit_amount, 4), "flops_per_launch": float(amount),
+            "us_per_launch": round(seconds * 1e6, 2), "algorithmic": note}
+
+
+def timed(torch, fn, reps, warmup=3):
+    """Average and p99 milliseconds of fn() from events on the current stream."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    return sum(ms) / len(ms), pct(ms, 99)
+
+
+def stress_leg(torch, reps=3):
+    """The full-resolution stress workload: the realistic generator at 2048^2
+    per view (about 7.55M Gaussians), C = 32, a 2048^2 target; four
+    consecutive frames whose features are perturbed by N(0, 0.05) (geometry
+    unchanged), each with its own dL/dF ~ N(0, 1), forward + adjoint served
+    as one batch of the request loop -- once letting frames 1-3 reuse frame
+    0's projection and sorted lists (their geometry is byte-identical), once
+    not.  Batch time = device completion observed by the server - batch
+    launch; beside it the plain path, frame by frame (forward + adjoint)."""
+    import numpy as np
+    import scenes
+    from paper_2405_14866_amd.rasterize import GaussianSoA, Rasterizer, empty_grads
+    from paper_2405_14866_amd.serve import Server
+    base = scenes.make_cfg5()
+    n, c, W, H = base.n, base.c, base.cam.width, base.cam.height
+    g0 = GaussianSoA.from_scene(base)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(51)
+    gs = [g0] + [GaussianSoA(g0.mean, g0.scale, g0.quat, g0.opacity,
+                             (g0.feat + 0.05 * torch.randn(g0.feat.shape, generator=gen, device="cuda")).contiguous())
+                 for _ in range(3)]
+    dFs = [torch.randn((c, H, W), generator=gen, device="cuda") for _ in range(4)]
+    outs = [(torch.empty((c, H, W), device="cuda"), torch.empty((H, W), device="cuda")) for _ in range(4)]
+    grads = [empty_grads(n, c) for _ in range(4)]
+    srv = Server(0, c=c, slots=1, max_batch=4, max_gauss_per_batch=4 * n + 8192,
+                 max_keys_per_batch=int(2.6 * 4 * n), max_pixels_per_batch=4 * W * H, max_side=max(W, H),
+                 keys_per_gaussian=2.5, batch_window_us=200000, backward=True)
+    res = {}
+    for share in (True, False):
+        batch_ms, shared = [], []
+        for rep in range(reps + 1):
+            ts = [srv.submit(g, base.cam, f, a, stream_id=0, d_feat=d, grads=gr, share=share)
+                  for g, (f, a), d, gr in zip(gs, outs, dFs, grads)]
+            rr = [srv.wait(t) for t in ts]
+            assert all(r.status == 0 and r.batch_size == 4 for r in rr), [(r.status, r.batch_size) for r in rr]
+            if rep > 0:                       # the first batch warms up (and captures the graph)
+                batch_ms.append((max(r.t_done_ns for r in rr) - min(r.t_launch_ns for r in rr)) * 1e-6)
+                shared.append(sum(r.shared for r in rr))
+        med = float(np.median(batch_ms))
+        res["with_sort_reuse" if share else "without_sort_reuse"] = {
+            "batch_ms": round(med, 3), "ms_per_frame": round(med / 4, 3), "frames_sharing": int(min(shared)),
+            "reps": reps}
+    srv.close()
+    rast = Rasterizer(0, max_n=n, max_w=W, max_h=H, keys_per_gaussian=2.5)
+    rast.forward(gs[0], base.cam)
+    fr = rast.frame.handle
+
+    def plain_frames():
+        for g, d in zip(gs, dFs):
+            f, a = rast.forward(g, base.cam, check=False)
+            rast.backward(g, d)
+
+    plain_ms, _ = timed(torch, plain_frames, reps, warmup=1)
+    res["plain_ms_per_frame"] = round(plain_ms / 4, 3)
+    res["workload"] = (f"{n} Gaussians (realistic generator, 4 x 2048^2 views), C = {c}, {W}x{H} target, "
+                       "4 frames forward + adjoint per batch")
+    res["n_keys"] = int(rast.n_keys)
+    return res
+
+
+def stereo_leg(torch, scene, g, reps):
+    """Both eyes of the user (64 mm apart around the frontal target, §4.2)
+    rendered together -- one projection reading each Gaussian once, one
+    binning, one blend launch -- against two single renders."""
+    import scenes
+    from paper_2405_14866_amd import _native as N
+    from paper_2405_14866_amd.rasterize import Rasterizer, camera_struct
+    n, c, W, H = scene.n, scene.c, scene.cam.width, scene.cam.height
+    eyes = scenes.stereo_pair(scene.cam)
+    cs = [camera_struct(e) for e in eyes]
+    r2 = Rasterizer(0, max_n=n, max_w=W, max_h=H, keys_per_gaussian=5.0, max_views=2)
+    r2.forward_views(g, eyes)
+    r1 = Rasterizer(0, max_n=n, max_w=W, max_h=H, keys_per_gaussian=5.0)
+    r1.forward(g, eyes[0])
+    r1.forward(g, eyes[1])
+    outs = [(torch.empty((c, H, W), device="cuda"), torch.empty((H, W), device="cuda")) for _ in eyes]
+    s = int(torch.cuda.current_stream().cuda_stream)
+    gs = g.struct()
+    f2, f1 = r2.frame.handle, r1.frame.handle
+
+    def pair():
+        N.tg_project_views(f2, gs, cs, s)
+        N.tg_bin_sort(f2, s)
+        N.tg_render_fwd_views(f2, gs, None, [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs], s)
+
+    def singles():
+        for cam, (f, a) in zip(cs, outs):
+            N.tg_project(f1, gs, cam, s)
+            N.tg_bin_sort(f1, s)
+            N.tg_render_fwd(f1, gs, None, f.data_ptr(), a.data_ptr(), s)
+
+    pair_ms, pair_p99 = timed(torch, pair, reps)
+    two_ms, _ = timed(torch, singles, reps)
+    for h in (f1, f2):
+        N.check(N.tg_frame_check(h)[0], "stereo capacity")
+    return {"pair_ms": round(pair_ms, 4), "pair_p99_ms": round(pair_p99, 4), "two_single_renders_ms": round(two_ms, 4),
+            "pair_over_two_singles": round(pair_ms / two_ms, 3), "ipd_m": 0.064,
+            "pairs_per_s": round(1e3 / pair_ms, 1)}
+
+
+def upstream_legs(torch, reps):
+    """The steps around the rasterizer, each against its HBM bound:
+    lifting the realistic frame's four 512^2 source views (C = 32) to
+    Gaussians (tg_lift); the cascaded disparity initialisation, view 0's
+    cloud splatted into views 2 and 3 (tg_zsplat); and at the paper's
+    2048^2 output resolution (four 2048^2 source views): the normals of the
+    four depth maps (tg_depth_normals), the fused depth of all lifted points
+    in the novel view (tg_zsplat) and the occlusion-aware blending
+    (tg_blend_views)."""
+    import numpy as np
+    import scenes
+    from paper_2405_14866_amd import _native as N
+    from paper_2405_14866_amd.lift import GaussianBuffers, Lifter, SourceViewMaps, zsplat
+    from paper_2405_14866_amd.rasterize import Context, camera_struct
+    out = {}
+    views = scenes.make_source_views(seed=12)
+    maps = [SourceViewMaps.from_source_view(v) for v in views]
+    pix = sum(v.mask.size for v in views)
+    lf = Lifter(0, max_pixels=pix)
+    buf = GaussianBuffers(pix, 32)
+    lf.enqueue(maps, buf)
+    torch.cuda.synchronize()
+    n = int(lf.n_out.item())
+    lift_views = [m.struct() for m in maps]
+    bstruct = buf.struct()
+    s0 = int(torch.cuda.current_stream().cuda_stream)
+    ms, _ = timed(torch, lambda: N.tg_lift(lf.handle, lift_views, 32, bstruct, lf.n_out.data_ptr(), s0), reps)
+    out["lift"] = roof("tg_lift (k_lift_count, k_lift_scan, k_lift_write)", "hbm",
+                       pix * 5 + n * (16 + 4 * 32) + n * (44 + 4 * 32), ms * 1e-3, None,
+                       "5 B per source pixel (mask, disparity) + 16 + 4C B per lifted pixel read "
+                       "+ 44 + 4C B per Gaussian written")
+    out["lift"]["gaussians"] = n
+    lf0 = Lifter(0, max_pixels=views[0].mask.size)
+    b0 = GaussianBuffers(views[0].mask.size, 32)
+    lf0.enqueue(maps[:1], b0)
+    torch.cuda.synchronize()
+    n0 = int(lf0.n_out.item())
+    pts = b0.view(n0).mean
+    cams = [views[2].cam, views[3].cam]
+    base = [views[2].baseline, views[3].baseline]
+    px2 = sum(cm.width * cm.height for cm in cams)
+    ctx = Context.get(0).handle
+    s = int(torch.cuda.current_stream().cuda_stream)
+    zb2, dp2 = torch.empty(px2, device="cuda"), torch.empty(px2, device="cuda")
+    cs2 = [camera_struct(cm) for cm in cams]
+    ms, _ = timed(torch, lambda: N.tg_zsplat(ctx, pts.data_ptr(), n0, cs2, base, zb2.data_ptr(), dp2.data_ptr(), s),
+                  reps)
+    out["zsplat_cascade"] = roof("tg_zsplat (cam0 cloud into two views)", "hbm", 12 * n0 + 8 * px2, ms * 1e-3, None,
+                                 "12 B per point + 8 B per target pixel (z-buffer, disparity)")
+    out["zsplat_cascade"]["points"] = n0
+    # 2048^2: normals, fused depth, blending
+    big = scenes.make_source_views(seed=55, src_res=2048, src_fx=2800.0, c=8)
+    novel = scenes.look_at_camera(0.0, 1.2, 2800.0, 1024.0, 2048).as_f32()
+    bpix = sum(v.mask.size for v in big)
+    lfb = Lifter(0, max_pixels=bpix)
+    bb = GaussianBuffers(bpix, 8)
+    lfb.enqueue([SourceViewMaps.from_source_view(v) for v in big], bb)
+    torch.cuda.synchronize()
+    nb = int(lfb.n_out.item())
+    depths = [torch.as_tensor(scenes.source_depth(v), device="cuda") for v in big]
+    nrm = [torch.empty(tuple(d.shape) + (3,), device="cuda") for d in depths]
+    cb = [camera_struct(v.cam) for v in big]
+    ms, _ = timed(torch, lambda: [N.tg_depth_normals(ctx, c_, d.data_ptr(), o.data_ptr(), s)
+                                  for c_, d, o in zip(cb, depths, nrm)], reps)
+    out["normals"] = roof("tg_depth_normals (4 x 2048^2)", "hbm", 16 * bpix, ms * 1e-3, None,
+                          "4 B depth in + 12 B normal out per source pixel")
+    bpts = bb.view(nb).mean
+    zfb = torch.empty(novel.width * novel.height, device="cuda")
+    cn = camera_struct(novel)
+    ms, _ = timed(torch, lambda: N.tg_zsplat(ctx, bpts.data_ptr(), nb, [cn], None, zfb.data_ptr(), None, s), reps)
+    out["zsplat_fused"] = roof("tg_zsplat (all points into the 2048^2 novel view)", "hbm",
+                               12 * nb + 4 * novel.width * novel.height, ms * 1e-3, None,
+                               "12 B per point + 4 B per novel pixel")
+    out["zsplat_fused"]["points"] = nb
+    (zf, _), = zsplat(bpts, [novel], None, with_disparity=False)
+    bviews, keep = [], []
+    for k, v in enumerate(big):
+        rgba = torch.as_tensor(scenes.source_rgba(v, 90 + k), device="cuda")
+        mk = torch.as_tensor(v.mask, device="cuda")
+        keep += [rgba, mk]
+        bv = N.tg_blend_view()
+        bv.cam, bv.rgba, bv.depth, bv.mask, bv.normal = cb[k], rgba.data_ptr(), depths[k].data_ptr(), \
+            mk.data_ptr(), nrm[k].data_ptr()
+        bviews.append(bv)
+    npx = novel.width * novel.height
+    rgb, ws = torch.empty(3 * npx, device="cuda"), torch.empty(npx, device="cuda")
+    ms, _ = timed(torch, lambda: N.tg_blend_views(ctx, bviews, cn, zf.data_ptr(), 0.02, rgb.data_ptr(),
+                                                  ws.data_ptr(), s), reps)
+    out["blend_views"] = roof("tg_blend_views (4 x 2048^2 views into 2048^2)", "hbm", 21 * bpix + 20 * npx,
+                              ms * 1e-3, None,
+                              "21 B per source pixel (RGBA, depth, mask, normal) + 20 B per novel pixel "
+                              "(fused depth in, RGB and weight sum out)")
+    torch.cuda.synchronize()
+    out["blend_views"]["pixels_blended"] = int((ws > 0).sum().item())
+    return out
 
 
 def main():
@@ -399,6 +765,17 @@ def main():
     # adjoint of the same frame: dL/dF ~ N(0, 1) seeded, gradients for every raw parameter
     bwd = backward_leg(fr, gs, scene, s, args.steps, args.warmup, step, torch)
     traffic, traffic_note = measured_traffic()
+    # every other kernel of the path against its own bound (algorithmic bytes)
+    kroof = [
+        roof("k_project (tg_project)", "hbm", n * (44 + 40), avg(proj_ms) * 1e-3, None,
+             "44 B per Gaussian in + 40 B of 2D state out"),
+        roof("k_count, k_scan, k_fill, k_sort (tg_bin_sort)", "hbm", int(nk) * 24, avg(bin_ms) * 1e-3, None,
+             "12 B per (tile, Gaussian) key written once and read once"),
+        roof("k_bwd_zero, k_render_bwd, k_project_bwd (tg_render_bwd)", "hbm",
+             W * H * (4 * c + 8) + n * (44 + 4 * c) + n * 4 * (11 + c), bwd["backward_ms"] * 1e-3, None,
+             "dL/dF (4C B) and T_final, last (8 B) per pixel in; 44 + 4C B per Gaussian in; "
+             "4 (11 + C) B of gradients per Gaussian out"),
+    ]
     out = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -432,8 +809,10 @@ def main():
                             "end_to_end_latency_ms": 150, "hardware": "1x RTX 4090",
                             "this_plain_frame_ms": round(ms_per_step, 4)}
     out["backward"] = bwd
+    out["kernel_rooflines"] = kroof
+    out["stereo_pair"] = stereo_leg(torch, scene, g, min(args.steps, 100))
     if not args.no_serve:
-        srv = serve_leg(scene, g, args.streams, args.steps, args.warmup, torch)
+        srv = serve_leg(scene, g, args.streams, max(args.serve_frames, args.steps), args.warmup, torch)
         out["serving"] = srv
         out["plain"] = {"frames_per_s": round(plain_fps, 2), "p50_ms": out["p50_ms"], "p99_ms": out["p99_ms"]}
         # the headline is the batched serving loop (throughput at saturation, latency
@@ -451,6 +830,10 @@ def main():
             "plain path (project -> bin_sort -> render, one frame per pass)",
             f"served by the batched loop ({args.streams} streams, resident Gaussians; frames/s "
             "with closed-loop clients, p50/p99 at a Poisson 240 frames/s); plain path beside it")
+    if not args.no_stress:
+        out["stress"] = stress_leg(torch)
+    if not args.no_upstream:
+        out["upstream"] = upstream_legs(torch, min(args.steps, 50))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds)
     print(json.dumps(out), flush=True)

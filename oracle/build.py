@@ -14,10 +14,17 @@ FLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
          "-ffp-contract=off", "-fno-fast-math", "-fno-finite-math-only"]
 
 
-def build(verbose: bool = False, out: str = LIB, plant: int = 0) -> str:
+# host-only sanitizer build (g++, no device code): AddressSanitizer and
+# UndefinedBehaviorSanitizer, every finding fatal
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, out: str = LIB, plant: int = 0, sanitize: bool = False) -> str:
     """Compile the oracle to `out`.  `plant` > 0 builds a deliberately wrong
-    variant (see the mutation hook in tgo.cpp), used only by the tests."""
-    cmd = ["g++", *FLAGS, f"-DTGO_PLANT={int(plant)}", SRC, "-o", out + ".tmp"]
+    variant (see the mutation hook in tgo.cpp), used only by the tests;
+    `sanitize` builds it with the sanitizers (load it with the ASan runtime
+    preloaded)."""
+    cmd = ["g++", *FLAGS, *(SANITIZE if sanitize else []), f"-DTGO_PLANT={int(plant)}", SRC, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
