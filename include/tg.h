@@ -116,7 +116,10 @@ void tg_ctx_destroy(tg_ctx* ctx);
  * up to max_n Gaussians, tile counters, up to max_keys (tile, Gaussian)
  * keys, and the per-pixel final transmittance and last-contributor index of
  * up to max_w x max_h pixels that the backward pass reads.  It is reused
- * across renders; one frame serves one stream at a time.  Allocates device
+ * across renders; one frame serves one stream at a time.  max_n rounded up
+ * to a multiple of 1024 (times max_views for tg_frame_create_views) is at
+ * most 2^28: the binning packs a 4-bit quadrant mask above the Gaussian
+ * index in its 32-bit index field (TG_ERR_INVALID beyond).  Allocates device
  * memory (TG_ERR_OOM on failure). */
 tg_status tg_frame_create(tg_ctx* ctx, int64_t max_n, int32_t max_w, int32_t max_h,
                           int64_t max_keys, tg_frame** out);
@@ -239,7 +242,7 @@ tg_status tg_render_bwd_views(tg_frame* frame, const tg_gaussians* g, const floa
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * render as tg_project + tg_bin_sort + tg_render_fwd on a frame (same
  * kernels, bit-identical results), with the workspace in a static device
- * array of TG_NOALLOC_SCRATCH_BYTES (86 MiB) instead of a tg_frame: no call
+ * array of TG_NOALLOC_SCRATCH_BYTES (150 MiB) instead of a tg_frame: no call
  * to hipMalloc, hipFree or any allocating routine.  Each device holds its
  * own array for the life of the process; tg_ctx_create resolves its address
  * on the context's device.  Limits: g->n <= TG_NOALLOC_MAX_N, width x height
@@ -256,7 +259,7 @@ tg_status tg_render_bwd_views(tg_frame* frame, const tg_gaussians* g, const floa
 #define TG_NOALLOC_MAX_KEYS 2097152
 #define TG_NOALLOC_MAX_PIXELS 1048576
 #define TG_NOALLOC_MAX_TILES 8192
-#define TG_NOALLOC_SCRATCH_BYTES 90309120
+#define TG_NOALLOC_SCRATCH_BYTES 157549056
 tg_status tg_render_noalloc(tg_ctx* ctx, const tg_gaussians* g, const tg_camera* cam, const float* bg,
                             float* out_feat, float* out_alpha, int32_t* status, void* stream);
 
@@ -415,7 +418,9 @@ typedef struct tg_serve_opts {
   int64_t budget_bytes;         /* device bytes the requests in flight may occupy */
   int32_t slots;                /* batches in flight at once (one HIP stream each), 1..8 */
   int32_t max_batch;            /* requests per batch, 1..64 */
-  int64_t max_gauss_per_batch;  /* slot workspace: Gaussians (sum over the batch) */
+  int64_t max_gauss_per_batch;  /* slot workspace: Gaussians (sum over the batch); rounded up
+                                   to a multiple of 1024, plus 1024 per request of max_batch,
+                                   at most 2^28 */
   int64_t max_keys_per_batch;   /* slot workspace: (tile, Gaussian) keys */
   int64_t max_pixels_per_batch; /* slot workspace: target pixels */
   int32_t max_side;             /* largest target width or height accepted */

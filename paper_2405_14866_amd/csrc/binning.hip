@@ -16,8 +16,12 @@
 //   k_fill   same LDS binning, then one global atomic per (workgroup, tile)
 //            reserves a contiguous run of the tile's segment and LDS
 //            atomics hand out slots inside it; each slot receives the 64-bit
-//            key (depth << 32) | index.  The order inside a segment is not
-//            deterministic here; the sort makes it so;
+//            key (depth << 32) | (quadrant mask << 28) | index, the mask
+//            holding the 8x8 quadrants of the tile that the Gaussian's alpha
+//            support can reach (the blend's conservative quadrant test,
+//            taken here while the Gaussian's mean and extents are in
+//            registers; indices stay below 2^28).  The order inside a
+//            segment is not deterministic here; the sort makes it so;
 //   k_sort   one 256-lane workgroup per tile, tiles taken longest first
 //            (the scan's order): the segment is loaded (eight keys per lane
 //            in flight at once) into LDS and sorted by a stable
@@ -33,14 +37,23 @@
 //            Segments up to 2048 keys run in a 32 KB-LDS launch (four
 //            workgroups per CU), larger ones in a second launch with 128 KB
 //            whose small grid walks the head of the tile order, and beyond
-//            8192 keys on global scratch buffers.
+//            8192 keys on global scratch buffers.  The sorted segment is
+//            written as the tile's index list and, from the same registers,
+//            split into four quadrant lists: entry j goes to the list of
+//            each quadrant its key's mask holds, in list order, as
+//            (index, j); the forward blend walks one quadrant per wave.
 //
 // Compared with a global LSD sort of all K keys (4-6 passes of K x 12-24 B
 // over HBM plus a launch per pass), the keys cross HBM about three times.
-#include "tg_internal.h"
+#include "blend_common.h"
 
 namespace tg {
 namespace {
+
+// low half of a key: quadrant mask in bits 28..31, Gaussian index below
+constexpr int KEY_MASK_SHIFT = 28;
+constexpr uint32_t KEY_INDEX = (1u << KEY_MASK_SHIFT) - 1u;
+static_assert(MAX_GAUSS_SPACE <= ((int64_t)1 << KEY_MASK_SHIFT), "indices fit below the quadrant mask");
 
 __device__ __forceinline__ void rect_of(uint2 r, int& x0, int& x1, int& y0, int& y1) {
   x0 = (int)(r.x & 0xffffu); x1 = (int)(r.x >> 16);
@@ -131,6 +144,14 @@ __global__ void __launch_bounds__(256) k_share_copy(BatchArgs a) {
     const int ts = batch_req(a, q.src - 1).tile_off + (t - q.tile_off);
     const int d = a.tile_start[t], n = a.tile_start[t + 1] - d, sidx = a.tile_start[ts];
     for (int j = threadIdx.x; j < n; j += 256) a.sorted[d + j] = a.sorted[sidx + j];
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      const int qn = a.qcount[4 * ts + qd];
+      const int2* src = a.qlist + 4 * (int64_t)sidx + (int64_t)qd * n;
+      int2* dst = a.qlist + 4 * (int64_t)d + (int64_t)qd * n;
+      for (int j = threadIdx.x; j < qn; j += 256) dst[j] = src[j];
+    }
+    if (threadIdx.x < 4) a.qcount[4 * t + threadIdx.x] = a.qcount[4 * ts + threadIdx.x];
   }
 }
 
@@ -190,6 +211,8 @@ __device__ __forceinline__ void scan_tiles(const BatchArgs& a, int nt, int per, 
       const int32_t v = over ? 0 : (int32_t)run;
       a.tile_start[b + k] = v;
       a.tile_cursor[b + k] = v;
+      // quadrant list lengths: the sort sets those of non-empty tiles
+      reinterpret_cast<int4*>(a.qcount)[b + k] = make_int4(0, 0, 0, 0);
       run += count(k);
     }
   }
@@ -255,11 +278,14 @@ __global__ void __launch_bounds__(1024) k_fill(BatchArgs a) {
     rect_of(a.rect[g], x0, x1, y0, y1);
     if (x0 > x1) continue;
     const uint64_t key = ((uint64_t)a.depth[g] << 32) | (uint64_t)(uint32_t)g;
+    const double2 xy = a.xy[g];
+    const float4 ext = a.ext[g];
     for (int ty = y0; ty <= y1; ++ty)
       for (int tx = x0; tx <= x1; ++tx) {
         const int t = ty * c.tiles_x + tx;
+        const uint32_t m = quadrant_mask(xy, ext, (double)(tx * TILE), (double)(ty * TILE));
         const int slot = lds ? atomicAdd(&bins[t], 1) : atomicAdd(&gcursor[t], 1);
-        a.keys[slot] = key;
+        a.keys[slot] = key | ((uint64_t)m << KEY_MASK_SHIFT);
       }
   }
 }
@@ -312,6 +338,7 @@ struct SortShared {
   uint32_t hist[4][256];   // per-wave digit counts, then running offsets
   uint32_t wtot[4];
   uint64_t red[4][4];
+  int32_t qw[4][4];        // per-wave quadrant counts of the output stage
 };
 
 // One stable pass over digit (key >> shift) & 255 of elements [0, n).
@@ -366,20 +393,68 @@ __device__ __forceinline__ Ptr radix_sort(Ptr a, Ptr b, int n, int shift0, int b
   return a;
 }
 
+// Output stage of a tile's sort.  get(j, gi, m) yields sorted entry j
+// (Gaussian index gi, quadrant mask m); the entry goes to the tile's index
+// list at s + j and to the list of each quadrant in m as (gi, j).  Rounds
+// of 256 entries: per quadrant a ballot per wave, the four wave counts in
+// LDS, and each entry's slot from the counts of the waves and lanes before
+// it, so every quadrant list keeps the list order.  Quadrant qd's list
+// starts at 4 s + qd n of qlist; its length goes to qcount[4 t + qd].
+template <typename Get>
+__device__ __forceinline__ void emit_sorted(const BatchArgs& a, int t, int s, int n, Get get, SortShared& sh) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int2* out = a.qlist + 4 * (int64_t)s;
+  const uint64_t below = lanemask_lt();
+  int base0 = 0, base1 = 0, base2 = 0, base3 = 0;
+  for (int j0 = 0; j0 < n; j0 += 256) {
+    const int j = j0 + tid;
+    uint32_t gi = 0, m = 0;
+    if (j < n) {
+      get(j, gi, m);
+      a.sorted[s + j] = (int32_t)gi;
+    }
+    uint64_t bal[4];
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) bal[qd] = __ballot((m >> qd) & 1u);
+    if (lane < 4) sh.qw[lane][w] = __popcll(bal[0]) * (lane == 0) + __popcll(bal[1]) * (lane == 1) +
+                                   __popcll(bal[2]) * (lane == 2) + __popcll(bal[3]) * (lane == 3);
+    __syncthreads();
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      int pre = 0, tot = 0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        const int v = sh.qw[qd][ww];
+        pre += ww < w ? v : 0;
+        tot += v;
+      }
+      int& base = qd == 0 ? base0 : (qd == 1 ? base1 : (qd == 2 ? base2 : base3));
+      if ((m >> qd) & 1u) out[(int64_t)qd * n + base + pre + __popcll(bal[qd] & below)] = make_int2((int)gi, j);
+      base += tot;
+    }
+    __syncthreads();                 // qw is reused by the next round
+  }
+  if (tid < 4) a.qcount[4 * t + tid] = tid == 0 ? base0 : (tid == 1 ? base1 : (tid == 2 ? base2 : base3));
+}
+
 constexpr int MAX_TIE_RUN = 32;
 
-// Segment sort of tiles whose key count lies in (lo, hi]: sort by depth
+// Segment sort of tile t, whose key count lies in (lo, hi]: sort by depth
 // alone (the key's high half, re-based to its minimum), then order each run
 // of equal depths by index; only a run longer than MAX_TIE_RUN makes the
 // tile redo the sort on the composite (depth, index) key.  Either way the
 // result is the (depth, index) order.  Segments above CAP run the
-// composite sort on the global scratch buffers.
+// composite sort on the global scratch buffers.  The quadrant mask rides
+// along: in the low half of the depth-only element (above the index, which
+// alone is compared among equal depths), below the composite key (whose
+// (depth, index) part is unique, so the mask never decides the order).
 template <int CAP>
-__device__ __forceinline__ void sort_tile(const BatchArgs& a, int s, int n, uint64_t* bufA, uint64_t* bufB,
+__device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int n, uint64_t* bufA, uint64_t* bufB,
                                           SortShared& sh) {
   const int tid = threadIdx.x, w = tid >> 6;
   if (n == 1) {
-    if (tid == 0) a.sorted[s] = (int32_t)(uint32_t)a.keys[s];
+    const uint32_t lo = (uint32_t)a.keys[s];
+    emit_sorted(a, t, s, 1, [&](int, uint32_t& gi, uint32_t& m) { gi = lo & KEY_INDEX; m = lo >> KEY_MASK_SHIFT; }, sh);
     return;
   }
   for (int q = tid; q < 4 * 256; q += 256) (&sh.hist[0][0])[q] = 0;
@@ -398,7 +473,7 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int s, int n, uint
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       if (j0 + tid + 256 * i < n) {
-        const uint64_t d = kv[i] >> 32, ix = kv[i] & 0xffffffffull;
+        const uint64_t d = kv[i] >> 32, ix = (uint32_t)kv[i] & KEY_INDEX;
         dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
         imin = ix < imin ? ix : imin; imax = ix > imax ? ix : imax;
       }
@@ -414,8 +489,18 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int s, int n, uint
   }
   const int db = bit_length(dmax - dmin), ib = bit_length(imax - imin);
   const uint64_t imask = ib == 0 ? 0ull : (~0ull >> (64 - ib));
+  // composite element: (depth - dmin, index - imin, mask), at most 32 + 28 + 4 bits
+  const int cbits = db + ib + 4;
+  auto composite = [&](uint64_t k) -> uint64_t {
+    return (((k >> 32) - dmin) << (ib + 4)) | ((((uint32_t)k & KEY_INDEX) - imin) << 4) |
+           (uint64_t)((uint32_t)k >> KEY_MASK_SHIFT);
+  };
+  auto from_composite = [&](uint64_t e, uint32_t& gi, uint32_t& m) {
+    gi = (uint32_t)(imin + ((e >> 4) & imask));
+    m = (uint32_t)e & 15u;
+  };
   if (n <= CAP) {
-    // depth-only pass set: element = (depth - dmin) << 32 | index
+    // depth-only pass set: element = (depth - dmin) << 32 | (mask, index)
     if (n <= 256 * PER) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
@@ -441,31 +526,33 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int s, int n, uint
       int end = j + 1;
       while (end < n && (res[end] >> 32) == dj && end - j <= MAX_TIE_RUN) ++end;
       if (end - j > MAX_TIE_RUN) { too_long = 1; continue; }
-      for (int p = j + 1; p < end; ++p) {        // same depth: compare the index half
+      for (int p = j + 1; p < end; ++p) {        // same depth: compare the index bits
         const uint64_t v = res[p];
+        const uint32_t vi = (uint32_t)v & KEY_INDEX;
         int q = p - 1;
-        while (q >= j && res[q] > v) { res[q + 1] = res[q]; --q; }
+        while (q >= j && ((uint32_t)res[q] & KEY_INDEX) > vi) { res[q + 1] = res[q]; --q; }
         res[q + 1] = v;
       }
     }
     if (__syncthreads_or(too_long)) {
-      for (int j = tid; j < n; j += 256) {
-        const uint64_t k = a.keys[s + j];
-        bufA[j] = (((k >> 32) - dmin) << ib) | ((k & 0xffffffffull) - imin);
-      }
+      for (int j = tid; j < n; j += 256) bufA[j] = composite(a.keys[s + j]);
       __syncthreads();
-      res = radix_sort<uint64_t*>(bufA, bufB, n, 0, db + ib, sh);
-      for (int j = tid; j < n; j += 256) a.sorted[s + j] = (int32_t)(imin + (res[j] & imask));
+      res = radix_sort<uint64_t*>(bufA, bufB, n, 0, cbits, sh);
+      emit_sorted(a, t, s, n, [&](int j, uint32_t& gi, uint32_t& m) { from_composite(res[j], gi, m); }, sh);
     } else {
-      for (int j = tid; j < n; j += 256) a.sorted[s + j] = (int32_t)(uint32_t)res[j];
+      emit_sorted(a, t, s, n, [&](int j, uint32_t& gi, uint32_t& m) {
+        const uint32_t lo = (uint32_t)res[j];
+        gi = lo & KEY_INDEX;
+        m = lo >> KEY_MASK_SHIFT;
+      }, sh);
     }
   } else {
     uint64_t* g0 = a.keys + s;
     uint64_t* g1 = a.keys_tmp + s;
-    for (int j = tid; j < n; j += 256) g0[j] = (((g0[j] >> 32) - dmin) << ib) | ((g0[j] & 0xffffffffull) - imin);
+    for (int j = tid; j < n; j += 256) g0[j] = composite(g0[j]);
     __syncthreads();
-    const uint64_t* res = radix_sort<uint64_t*>(g0, g1, n, 0, db + ib, sh);
-    for (int j = tid; j < n; j += 256) a.sorted[s + j] = (int32_t)(imin + (res[j] & imask));
+    const uint64_t* res = radix_sort<uint64_t*>(g0, g1, n, 0, cbits, sh);
+    emit_sorted(a, t, s, n, [&](int j, uint32_t& gi, uint32_t& m) { from_composite(res[j], gi, m); }, sh);
   }
 }
 
@@ -490,7 +577,7 @@ __global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
     }
     if (n > hi) continue;
     if (h.n_shared > 0 && batch_req(a, req_of_tile(a, h, t)).src != 0) continue;   // copied later
-    sort_tile<CAP>(a, s, n, bufA, bufB, sh);
+    sort_tile<CAP>(a, t, s, n, bufA, bufB, sh);
     __syncthreads();                 // LDS is reused by the next tile
   }
 }

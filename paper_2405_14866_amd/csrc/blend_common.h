@@ -22,11 +22,32 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // formed here in FP64 from the FP64 mean.  mask: bit q set when the
 // alpha >= 1/255 ellipse (half-extents ext.xy, widened by CULL_MARGIN so no
 // pixel that could pass is culled) reaches the 8x8 quadrant q of the tile.
+// The binning applies the same test when it splits each tile's sorted list
+// into the four quadrant lists the forward blend walks.
 struct TileState {
   float c1, c2;
   float u, v;                 // tile-relative mean (the adjoint's moments)
   uint32_t mask;
 };
+
+// Quadrants of the tile at (ox, oy) that the alpha >= 1/255 ellipse of a
+// Gaussian (FP64 mean xy, half-extents ext.xy) can reach, from the
+// tile-relative mean (u, v) rounded to float32.
+__device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float4 ext) {
+  const float ex = ext.x + CULL_MARGIN, ey = ext.y + CULL_MARGIN;   // -inf: no support
+  uint32_t mask = 0;
+#pragma unroll
+  for (int qd = 0; qd < 4; ++qd) {
+    const float x0 = (float)((qd & 1) * 8) + 0.5f, y0 = (float)((qd >> 1) * 8) + 0.5f;
+    const bool hit = (u + ex >= x0) && (u - ex <= x0 + 7.f) && (v + ey >= y0) && (v - ey <= y0 + 7.f);
+    mask |= hit ? (1u << qd) : 0u;
+  }
+  return mask;
+}
+
+__device__ __forceinline__ uint32_t quadrant_mask(double2 xy, float4 ext, double ox, double oy) {
+  return quadrant_mask((float)(xy.x - ox), (float)(xy.y - oy), ext);
+}
 
 __device__ __forceinline__ TileState make_state(double2 xy, float4 wq, float4 ext, double ox, double oy) {
   TileState t;
@@ -35,16 +56,14 @@ __device__ __forceinline__ TileState make_state(double2 xy, float4 wq, float4 ex
   t.c2 = (float)(-(double)wq.z * dv);
   t.u = (float)du;
   t.v = (float)dv;
-  const float ex = ext.x + CULL_MARGIN, ey = ext.y + CULL_MARGIN;   // -inf: no support
-  uint32_t mask = 0;
-#pragma unroll
-  for (int qd = 0; qd < 4; ++qd) {
-    const float x0 = (float)((qd & 1) * 8) + 0.5f, y0 = (float)((qd >> 1) * 8) + 0.5f;
-    const bool hit = (t.u + ex >= x0) && (t.u - ex <= x0 + 7.f) && (t.v + ey >= y0) && (t.v - ey <= y0 + 7.f);
-    mask |= hit ? (1u << qd) : 0u;
-  }
-  t.mask = mask;
+  t.mask = quadrant_mask(t.u, t.v, ext);
   return t;
+}
+
+// c1, c2 of make_state alone (the quadrant lists are already culled)
+__device__ __forceinline__ float2 exponent_offsets(double2 xy, float4 wq, double ox, double oy) {
+  const double du = xy.x - ox, dv = xy.y - oy;
+  return make_float2((float)(-((double)wq.x * du + (double)wq.y * dv)), (float)(-(double)wq.z * dv));
 }
 
 // log2 of the opacity-weighted Gaussian at tile-local pixel centre

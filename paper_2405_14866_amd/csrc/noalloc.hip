@@ -7,7 +7,7 @@
 // The workspace is one file-scope __device__ array, `scratch`, sized for the
 // largest render it accepts (the TG_NOALLOC_MAX_* limits of include/tg.h:
 // 524,288 Gaussians, 2,097,152 (tile, Gaussian) keys, 1,048,576 pixels,
-// 8,192 tiles; 86 MiB).  Each device the library runs on holds its own copy
+// 8,192 tiles; 150 MiB).  Each device the library runs on holds its own copy
 // for the life of the process.  Host code never names the array except to
 // ask for its device address: tg_ctx_create calls noalloc_setup with the
 // context's device current, which resolves the address once per device
@@ -38,7 +38,7 @@ constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 struct Layout {
   size_t xy, conic_o, wq, ext, rect, depth;
   size_t tile_count, tile_start, tile_cursor, tile_order;
-  size_t keys, keys_tmp, sorted;
+  size_t keys, keys_tmp, sorted, qlist, qcount;
   size_t T_final, last, dev, total;
 };
 
@@ -58,6 +58,8 @@ constexpr Layout make_layout() {
   l.keys = o;        o += align256(NA_MAX_KEYS * sizeof(uint64_t));
   l.keys_tmp = o;    o += align256(NA_MAX_KEYS * sizeof(uint64_t));
   l.sorted = o;      o += align256(NA_MAX_KEYS * sizeof(int32_t));
+  l.qlist = o;       o += align256(4 * NA_MAX_KEYS * sizeof(int2));
+  l.qcount = o;      o += align256(4 * NA_MAX_TILES * sizeof(int32_t));
   l.T_final = o;     o += align256(NA_MAX_PIXELS * sizeof(float));
   l.last = o;        o += align256(NA_MAX_PIXELS * sizeof(int32_t));
   l.dev = o;         o += align256(sizeof(FrameDev));
@@ -67,6 +69,7 @@ constexpr Layout make_layout() {
 
 constexpr Layout LAYOUT = make_layout();
 static_assert(LAYOUT.total == TG_NOALLOC_SCRATCH_BYTES, "the header states the array's size");
+static_assert(NA_MAX_N <= MAX_GAUSS_SPACE, "Gaussian indices fit the binning's keys");
 
 // The workspace.  In host code this name is only a handle for
 // hipGetSymbolAddress; its device address is looked up per device.
@@ -180,6 +183,8 @@ extern "C" tg_status tg_render_noalloc(tg_ctx* ctx, const tg_gaussians* g, const
   a.keys = at<uint64_t>(base, LAYOUT.keys);
   a.keys_tmp = at<uint64_t>(base, LAYOUT.keys_tmp);
   a.sorted = at<int32_t>(base, LAYOUT.sorted);
+  a.qlist = at<int2>(base, LAYOUT.qlist);
+  a.qcount = at<int32_t>(base, LAYOUT.qcount);
   a.g2d = nullptr;                       // forward only: no adjoint accumulators
   a.g_cap = NA_MAX_N;
   a.key_cap = NA_MAX_KEYS;

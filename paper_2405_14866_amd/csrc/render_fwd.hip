@@ -1,45 +1,38 @@
 // render_fwd.hip -- step 3 of the rasterizer: per-tile front-to-back blend
 // of C-channel latent features (gfx950).
 //
-// Persistent workgroups of 256 lanes (4 wave64) take tiles of the batch's
-// global tile space from a device work queue, longest tiles first; one
-// pixel per lane, wave w owns the 8x8 quadrant (w & 1, w >> 1) of the tile.
-// The tile's sorted Gaussian list is consumed in batches of B entries,
-// double-buffered in LDS:
-//   * while batch b is blended, batch b+1 is fetched by LDS DMA
-//     (global_load_lds_dwordx4): its feature rows as 16-byte chunks over
-//     the four waves, its FP64 mean, exponent factors and support extents
-//     (one 16-byte load per entry each), straight into the other buffer
-//     without passing through VGPRs; the list indices of batch b+2 come
-//     into a register.  The two buffers are separate LDS objects and the
-//     batch loop is unrolled by two, so the compiler can tell the DMA target
-//     from the buffer being walked and the walk never waits for the DMA;
-//     each wave waits for its own DMA before the barrier that ends the batch;
-//   * the kernel asks for five waves per SIMD: latency, not issue, bounds
-//     the walk, and the registers of five waves leave room to fetch both
-//     entries' feature slices at the top of a walk iteration, so that their
-//     LDS latency overlaps the exponents and decisions;
+// Work item = one 8x8 quadrant of a 16x16 tile, one wave64 per item, one
+// pixel per lane.  The binning leaves, for every quadrant, the sub-list of
+// its tile's sorted list whose alpha >= 1/255 support can reach the
+// quadrant (a conservative bounding-box test widened by 1/16 px), in list
+// order, as (Gaussian index, tile-list position); walking that sub-list
+// gives exactly the pixels' walk over the whole tile list, because every
+// entry left out is skipped by all 64 pixels.  The waves of a workgroup are
+// independent: each takes its items from a fixed assignment over the tile
+// order (tiles longest first; see k_render) and never waits for another
+// wave, so a quadrant with a long list holds up nobody.
+//   * the quadrant list is consumed in batches of B entries (B = 24 at
+//     C = 32: two 3 KB feature buffers per wave, five 4-wave workgroups per
+//     CU): while batch b is walked, batch b+1's feature rows arrive in the
+//     wave's other LDS buffer by LDS DMA (global_load_lds_dwordx4, C/4 lanes
+//     per row), its FP64 mean and exponent factors and the entries of batch
+//     b+2 load into registers; after the walk batch b+1's tile-dependent
+//     offsets are formed and staged in the wave's LDS, and the wave waits
+//     for its own DMA only;
 //   * per staged Gaussian the walk reads the projection's exponent factors
 //     (s, s k, r, log2 o) and the tile-dependent offsets (c1, c2), formed in
 //     FP64 from the FP64 mean relative to the tile origin (so pixel offsets
 //     are accurate to ~1e-7 px); log2 of the opacity-weighted Gaussian at a
 //     pixel is then log2 o - z1^2 - z2^2 with z1, z2 affine in the pixel
-//     centre: five FMAs and one v_exp_f32 give o G.  make_state also forms a
-//     4-bit mask of the quadrants its alpha >= 1/255 ellipse can reach
-//     (bounding box widened by 1/16 px, so no pixel that could pass the
-//     threshold is ever culled and the blend's decisions are those of the
-//     plain walk);
-//   * each wave ballots the quadrant bits of the batch and walks only the
-//     Gaussians that reach its quadrant, in list order (s_ff1 over the
-//     ballot mask), so Gaussians that only touch the other quadrants cost
-//     it nothing; a wave whose pixels have all ended walks nothing more;
-//   * the walk takes two reaching Gaussians per iteration: their alphas are
+//     centre: five FMAs and one v_exp_f32 give o G;
+//   * the walk takes two entries per iteration: their alphas are
 //     independent and overlap, then their decisions and feature
 //     accumulations run in list order.  A pixel's threshold test is one
 //     compare against its own minimum alpha (1/255 while it runs, 2 once it
 //     has ended, so an ended pixel fails every later test); the state
 //     updates of a blend and its feature accumulation sit behind a
-//     wave-uniform branch, since many steps blend in few pixels;
+//     wave-uniform branch, since many steps blend in few pixels; a wave whose
+//     pixels have all ended stops;
 //   * the feature accumulation of a step is the rank-1 update F += w f^T of
 //     the wave's 64 pixels x C channels (w: each lane's blend weight, 0 where
 //     it does not blend).  It runs on the matrix cores as C/4
@@ -51,13 +44,14 @@
 //     the C FMAs per step off the VALU and cuts the LDS bytes of a step
 //     four-fold; the background enters as one last update with weight T.
 // Per pixel: alpha = min(0.99, o G); skip when alpha < 1/255; a Gaussian
-// that would take T below 1e-4 ends the pixel without being blended.
+// that would take T below 1e-4 ends the pixel without being blended.  The
+// last blended Gaussian's position in the tile's list is kept for the
+// adjoint.
 #include "blend_common.h"
 
 namespace tg {
 namespace {
 
-constexpr int RENDER_B = 64;             // Gaussians per staged batch
 constexpr int PERSISTENT_WG = 256 * 8;   // persistent workgroups (>= resident capacity)
 
 
@@ -84,76 +78,59 @@ struct WorkCount {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// LDS of one staged batch (one of two, each a separate __shared__ object so
-// that the compiler can tell the DMA into one from the walk over the other)
+// One wave's LDS: the feature rows of two batches (the one being walked
+// and the next, arriving by LDS DMA) and the staged state of the batch being
+// walked.  Four waves of a workgroup hold four of these and share nothing.
 template <int C, int B>
-struct BatchLDS {
-  float4 wq[B];                     // exponent factors, DMA target (walked as they are)
-  double2 xy[B];                    // FP64 mean, DMA target
-  float4 ext[B];                    // support half-extents, DMA target
-  float4 st[B];                     // (c1, c2, quadrant mask bits, -) from make_state
-  int32_t ix[B];                    // Gaussian indices
-  __align__(16) float fe[B * C];    // feature rows, DMA target
+struct WaveLDS {
+  __align__(16) float fe[2][B * C];  // feature rows, DMA targets
+  float4 wq[B];                      // exponent factors
+  float4 st[B];                      // (c1, c2, tile-list position as bits, -)
 };
 
-// Issue the DMA of batch entries [0, nb) (indices in L.ix): feature rows
-// as 16-byte chunks spread over the four waves; the mean by wave 0, the
-// exponent factors by wave 1 and the extents by wave 2 (one 16-byte load
-// per lane each).
+// Entries per batch: two feature buffers of 3 KB (C >= 16), so that five
+// workgroups of four waves fit a CU's LDS.
+template <int C>
+constexpr int wave_batch() { return C >= 64 ? 12 : (C == 32 ? 24 : (C == 16 ? 48 : 64)); }
+
+// Issue the LDS DMA of the feature rows of a batch (entries [0, nb); lane j
+// holds entry j's global index gi) into buffer dst: 16-byte chunks, C / 4
+// lanes per row, 64 / (C / 4) rows per instruction.  Rows past nb read row
+// 0's address (in bounds) and are never walked.
 template <int C, int B>
-__device__ __forceinline__ void dma_batch(const BatchArgs& a, const float* __restrict__ feat, int64_t g_off,
-                                          BatchLDS<C, B>& L, int nb, int w, int lane) {
-  constexpr int CHUNKS = C / 4;
-  constexpr int INSTR = B * CHUNKS / 64;     // wave-wide feature loads per batch
-  constexpr int PER = (INSTR + 3) / 4;       // ... per wave
-  // all index reads first: an LDS read after a DMA into the same object
-  // would have to wait for the DMA
-  const int g0 = L.ix[lane < nb ? lane : 0];
-  int gi[PER];
+__device__ __forceinline__ void dma_rows(const float* __restrict__ feat, int64_t g_off, float* dst, int gi, int nb,
+                                         int lane) {
+  constexpr int LPR = C / 4;
+  constexpr int RPI = 64 / LPR;
+  static_assert(B % RPI == 0, "a batch is a whole number of DMA instructions");
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int q = (w + 4 * i) * 64 + lane;
-    const int r = q / CHUNKS;
-    gi[i] = L.ix[r < nb ? r : 0];
-  }
-  if (w == 0) __builtin_amdgcn_global_load_lds((const void*)(a.xy + g0), (lds_void*)L.xy, 16, 0, 0);
-  if (w == 1) __builtin_amdgcn_global_load_lds((const void*)(a.wq + g0), (lds_void*)L.wq, 16, 0, 0);
-  if (w == 2) __builtin_amdgcn_global_load_lds((const void*)(a.ext + g0), (lds_void*)L.ext, 16, 0, 0);
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int k = w + 4 * i;
-    if (k < INSTR) {
-      const int p = ((k * 64 + lane) % CHUNKS);
-      __builtin_amdgcn_global_load_lds((const void*)(feat + (int64_t)(gi[i] - g_off) * C + 4 * p),
-                                       (lds_void*)(L.fe + k * 256), 16, 0, 0);
-    }
+  for (int k = 0; k < B / RPI; ++k) {
+    const int row = k * RPI + lane / LPR;
+    const int g = __shfl(gi, row < nb ? row : 0, 64);
+    if (k * RPI < nb)
+      __builtin_amdgcn_global_load_lds((const void*)(feat + (g - g_off) * C + 4 * (lane % LPR)),
+                                       (lds_void*)(dst + k * 256), 16, 0, 0);
   }
 }
 
-// tile-dependent state of entry t of a staged batch
-template <int C, int B>
-__device__ __forceinline__ void stage_state(BatchLDS<C, B>& L, int t, double ox, double oy) {
-  const TileState ts = make_state(L.xy[t], L.wq[t], L.ext[t], ox, oy);
-  L.st[t] = make_float4(ts.c1, ts.c2, __uint_as_float(ts.mask), 0.f);
-}
-
-// Blend one tile (tile-local coordinates tx, ty of request q).
+// Blend the 8x8 quadrant qd of one tile (tile-local coordinates tx, ty of
+// request q) with one wave, walking the quadrant's list.
 template <int C, int B, bool COUNT>
-__device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q, int gtile, int tx,
-                                            int ty, BatchLDS<C, B>& L0, BatchLDS<C, B>& L1, WorkCount& wc) {
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+__device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev& q, int gtile, int tx, int ty,
+                                                int qd, WaveLDS<C, B>& L, WorkCount& wc) {
+  const int lane = threadIdx.x & 63;
   const int W = q.cam.W, H = q.cam.H;
-  const int lx = ((w & 1) << 3) | (lane & 7);
-  const int ly = ((w >> 1) << 3) | (lane >> 3);
+  const int lx = ((qd & 1) << 3) | (lane & 7);
+  const int ly = ((qd >> 1) << 3) | (lane >> 3);
   const int px = tx * TILE + lx, py = ty * TILE + ly;
   const bool inside = px < W && py < H;
   const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
   const double ox = (double)(tx * TILE), oy = (double)(ty * TILE);
-  const int s = a.tile_start[gtile], e = a.tile_start[gtile + 1];
-  const int len = e - s;
-  const uint32_t qbit = 1u << w;
+  const int s = a.tile_start[gtile], len = a.tile_start[gtile + 1] - s;
+  const int qn = a.qcount[4 * gtile + qd];
+  const int2* ql = a.qlist + 4 * (int64_t)s + (int64_t)qd * len;
   const float* feat = q.feat;
-  const int64_t g_off = q.s_off;      // the list holds indices of this 2D-state range
+  const int64_t g_off = q.s_off;      // the lists hold indices of this 2D-state range
 
   constexpr int NM = C / 4;           // MFMA updates per blend step
   const int q4 = lane & 3;
@@ -167,25 +144,9 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
   float amin = inside ? ALPHA_MIN : 2.f;
   int stop_pos = -1;                  // list position that ended the pixel (COUNT only)
 
-  const int nbatch = (len + B - 1) / B;
-  // prologue: indices of batches 0 and 1, batch 0 fetched and staged
-  if (tid < B) {
-    L0.ix[tid] = tid < len ? a.sorted[s + tid] : 0;
-    L1.ix[tid] = B + tid < len ? a.sorted[s + B + tid] : 0;
-  }
-  __syncthreads();
-  if (nbatch > 0) {
-    dma_batch<C, B>(a, feat, g_off, L0, min(B, len), w, lane);
-    __builtin_amdgcn_s_waitcnt(0);
-  }
-  __syncthreads();
-  if (tid < B && tid < len) stage_state<C, B>(L0, tid, ox, oy);
-  __syncthreads();
-
-  // One list entry (position pos) against this wave's pixels, given its
-  // alpha and feature slice: the stop / blend decisions, then the state
-  // updates and the feature accumulation behind a wave-uniform branch
-  // (most steps blend in only some of the pixels).
+  // One list entry (tile-list position pos) against this wave's pixels,
+  // given its alpha and feature slice: the stop / blend decisions, then the
+  // state updates and the feature accumulation behind a wave-uniform branch.
   auto visit = [&](const float (&fl)[NM], int pos, float al, bool valid) {
     const bool ok = valid & (al >= amin);
     const float Tn = __builtin_fmaf(-al, T, T);
@@ -205,57 +166,69 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     }
   };
 
-  auto step = [&](BatchLDS<C, B>& cur, BatchLDS<C, B>& nxt, int b) -> bool {
-    const int b0 = b * B;
-    const int nb = min(B, len - b0);
-    const bool more = b + 1 < nbatch;
-    const int nb1 = more ? min(B, len - b0 - B) : 0;
-    // ---- batch b+1 on its way into LDS; indices of batch b+2 into a register
-    if (more) dma_batch<C, B>(a, feat, g_off, nxt, nb1, w, lane);
-    int pidx = 0;
-    if (more && tid < B && b0 + 2 * B + tid < len) pidx = a.sorted[s + b0 + 2 * B + tid];
-    // ---- blend batch b: walk the Gaussians that reach this wave's quadrant
-    // (none once every pixel of the wave has ended)
-    {
-      const bool live = __builtin_amdgcn_ballot_w64(amin < 1.f) != 0;
-      const bool reach = live && lane < nb && (__float_as_uint(cur.st[lane].z) & qbit) != 0;
-      uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
-      // two reaching Gaussians per iteration: their alphas are independent
-      // and overlap; the decisions and accumulations then run in list order
-      while (mask) {
-        const int j1 = (int)__builtin_ctzll(mask);
-        mask &= mask - 1;
-        const bool has2 = mask != 0;
-        const int j2 = has2 ? (int)__builtin_ctzll(mask) : j1;
-        if (has2) mask &= mask - 1;
-        // feature slices of both entries first (see load_slice)
-        float fl1[NM], fl2[NM];
-        load_slice<NM>(cur.fe + j1 * C + NM * q4, fl1);
-        load_slice<NM>(cur.fe + j2 * C + NM * q4, fl2);
-        const float4 w1 = cur.wq[j1], w2 = cur.wq[j2];
-        const float2 c1 = *reinterpret_cast<const float2*>(&cur.st[j1]);
-        const float2 c2 = *reinterpret_cast<const float2*>(&cur.st[j2]);
-        const float al1 = blend_alpha(exponent(w1, c1.x, c1.y, fpx, fpy));
-        const float al2 = blend_alpha(exponent(w2, c2.x, c2.y, fpx, fpy));
-        if (COUNT) wc.steps += has2 ? 2 : 1;
-        visit(fl1, b0 + j1, al1, true);
-        visit(fl2, b0 + j2, al2, has2);
-      }
+  const int nbatch = (qn + B - 1) / B;
+  // prologue: batch 0's rows on their way, its state staged; batch 1's entries in a register
+  int2 e = lane < B && lane < qn ? ql[lane] : make_int2(0, 0);
+  int2 en = lane < B && B + lane < qn ? ql[B + lane] : make_int2(0, 0);
+  if (nbatch > 0) {
+    dma_rows<C, B>(feat, g_off, L.fe[0], e.x, min(B, qn), lane);
+    if (lane < B && lane < qn) {
+      const double2 xy = a.xy[e.x];
+      const float4 wq = a.wq[e.x];
+      const float2 cc = exponent_offsets(xy, wq, ox, oy);
+      L.wq[lane] = wq;
+      L.st[lane] = make_float4(cc.x, cc.y, __int_as_float(e.y), 0.f);
     }
-    // ---- finish batch b+1: every wave's DMA complete, then its 2D state
     __builtin_amdgcn_s_waitcnt(0);
-    const int alive = __syncthreads_count(amin < 1.f);
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int b = 0; b < nbatch; ++b) {
+    const int b0 = b * B;
+    const int nb = min(B, qn - b0);
+    const bool more = b + 1 < nbatch;
+    const int nb1 = more ? min(B, qn - b0 - B) : 0;
+    float* cur = L.fe[b & 1];
+    // ---- batch b+1: its rows on their way into the other buffer, its
+    // state and the entries of batch b+2 loading into registers
+    double2 nxy = make_double2(0.0, 0.0);
+    float4 nwq = make_float4(0.f, 0.f, 0.f, 0.f);
+    int2 en2 = make_int2(0, 0);
     if (more) {
-      if (tid < nb1) stage_state<C, B>(nxt, tid, ox, oy);
-      if (tid < B) cur.ix[tid] = pidx;
+      dma_rows<C, B>(feat, g_off, L.fe[(b + 1) & 1], en.x, nb1, lane);
+      if (lane < nb1) {
+        nxy = a.xy[en.x];
+        nwq = a.wq[en.x];
+      }
+      if (lane < B && b0 + 2 * B + lane < qn) en2 = ql[b0 + 2 * B + lane];
     }
-    __syncthreads();
-    return alive != 0;
-  };
-  for (int b = 0; b < nbatch; b += 2) {
-    if (!step(L0, L1, b)) break;
-    if (b + 1 >= nbatch) break;
-    if (!step(L1, L0, b + 1)) break;
+    // ---- walk batch b, two entries per iteration: their alphas are
+    // independent and overlap; the decisions and accumulations run in list order
+    for (int j = 0; j < nb; j += 2) {
+      const int j2 = j + 1 < nb ? j + 1 : j;
+      const bool has2 = j + 1 < nb;
+      float fl1[NM], fl2[NM];
+      load_slice<NM>(cur + j * C + NM * q4, fl1);
+      load_slice<NM>(cur + j2 * C + NM * q4, fl2);
+      const float4 w1 = L.wq[j], w2 = L.wq[j2];
+      const float4 s1 = L.st[j], s2 = L.st[j2];
+      const float al1 = blend_alpha(exponent(w1, s1.x, s1.y, fpx, fpy));
+      const float al2 = blend_alpha(exponent(w2, s2.x, s2.y, fpx, fpy));
+      if (COUNT) wc.steps += has2 ? 2 : 1;
+      visit(fl1, __float_as_int(s1.z), al1, true);
+      visit(fl2, __float_as_int(s2.z), al2, has2);
+    }
+    const bool live = __builtin_amdgcn_ballot_w64(amin < 1.f) != 0;
+    // ---- stage batch b+1's state (batch b's is no longer read)
+    __builtin_amdgcn_wave_barrier();
+    if (more && lane < nb1) {
+      const float2 cc = exponent_offsets(nxy, nwq, ox, oy);
+      L.wq[lane] = nwq;
+      L.st[lane] = make_float4(cc.x, cc.y, __int_as_float(en.y), 0.f);
+    }
+    en = en2;
+    __builtin_amdgcn_s_waitcnt(0);    // batch b+1's rows have landed
+    __builtin_amdgcn_wave_barrier();
+    if (!live) break;                 // every pixel of the quadrant has ended
   }
   if (q.bg) {                         // F += T_final bg, as one more rank-1 update
     float bl[NM];
@@ -275,8 +248,8 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     // which are consecutive in one row of the quadrant
     const size_t HW = (size_t)W * H;
     const int b4 = lane & ~3;
-    const int px0 = tx * TILE + ((w & 1) << 3) + (b4 & 7);
-    const int py0 = ty * TILE + ((w >> 1) << 3) + (b4 >> 3);
+    const int px0 = tx * TILE + ((qd & 1) << 3) + (b4 & 7);
+    const int py0 = ty * TILE + ((qd >> 1) << 3) + (b4 >> 3);
     if (py0 < H) {
       float* base = q.out_feat + (size_t)py0 * W + px0;
       if (px0 + 3 < W && (W & 3) == 0) {
@@ -294,64 +267,58 @@ __device__ __forceinline__ void render_tile(const BatchArgs& a, const ReqDev& q,
     }
   }
   if (COUNT && inside) {
-    // evaluated pairs of the plain walk: every list position up to the stop
+    // evaluated pairs of the plain walk over the tile's list: every list
+    // position up to the stop
     wc.n_eval += stop_pos >= 0 ? (uint32_t)(stop_pos + 1) : (uint32_t)len;
   }
-  __syncthreads();                    // LDS buffers are reused by the next tile
 }
 
-// TABLE: the batch's requests come from the device table (a replayed
-// serving batch) rather than inline (a single render); the two are separate
-// instantiations so that each keeps its own launch statistics.
-template <int C, int B, bool COUNT, bool TABLE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_render(BatchArgs a) {
+// Persistent workgroups of four independent waves.  Work item i is quadrant
+// i & 3 of the tile at position i >> 2 of the tile order (longest tiles
+// first); wave w of workgroup b takes items 4 b + w, 4 (b + G) + w, ... for
+// a grid of G workgroups, so the four waves of a workgroup blend the four
+// quadrants of one tile (sharing its Gaussians in the CU's cache) and each
+// blends alone, without a workgroup barrier.  The assignment is static: one
+// device-wide atomic counter handing out items to every wave serialises at
+// that counter (measured: it doubled the blend's time), while the longest-
+// first order plus the hardware's dispatch of the workgroups beyond the
+// resident ones keeps the load even.  TABLE: the batch's requests come from
+// the device table (a replayed serving batch) rather than inline (a single
+// render); the two are separate instantiations so that each keeps its own
+// launch statistics.
+template <int C, bool COUNT, bool TABLE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_render(BatchArgs a) {
   if (a.dev->overflow) return;
   if (!TABLE) a.table = nullptr;
   const BatchHdr h = batch_hdr(a);
-  __shared__ BatchLDS<C, B> L0;
-  __shared__ BatchLDS<C, B> L1;
-  __shared__ int s_tile;
-  const int tid = threadIdx.x;
+  constexpr int B = wave_batch<C>();
+  __shared__ WaveLDS<C, B> LW[4];
+  const int lane = threadIdx.x & 63;
+  WaveLDS<C, B>& L = LW[threadIdx.x >> 6];
   WorkCount wc;
-  for (;;) {
-    if (tid == 0) {                  // queue position -> tile, longest tiles first
-      const int k = atomicAdd(&a.dev->tile_queue, 1);
-      s_tile = k < h.n_tiles ? a.tile_order[k] : -1;
-    }
-    __syncthreads();
-    const int t = s_tile;
-    __syncthreads();
-    if (t < 0) break;
+  const int n_items = 4 * h.n_tiles;
+  for (int item = 4 * (int)blockIdx.x + (int)(threadIdx.x >> 6); item < n_items; item += 4 * (int)gridDim.x) {
+    const int t = a.tile_order[item >> 2];
     const int r = req_of_tile(a, h, t);
     if (r < 0) break;
     const ReqDev& q = batch_req(a, r);
     const int lt = t - q.tile_off;
-    render_tile<C, B, COUNT>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, L0, L1, wc);
+    render_quadrant<C, B, COUNT>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, item & 3, L, wc);
   }
   if (COUNT) {
-    __shared__ unsigned long long cnt[5];
-    if (tid < 5) cnt[tid] = 0;
-    __syncthreads();
-    atomicAdd(&cnt[0], (unsigned long long)wc.n_eval);
-    atomicAdd(&cnt[1], (unsigned long long)wc.n_blend);
-    if ((tid & 63) == 0) {
-      atomicAdd(&cnt[2], (unsigned long long)wc.steps);
-      atomicAdd(&cnt[3], (unsigned long long)wc.steps_pass);
-      atomicAdd(&cnt[4], (unsigned long long)wc.steps_blend);
+    // wave sums of the lane counts, then one atomic per wave and count
+    unsigned long long v[5] = {wc.n_eval, wc.n_blend, wc.steps, wc.steps_pass, wc.steps_blend};
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if (lane == 0) {
+      atomicAdd(&a.dev->n_eval, v[0]);
+      atomicAdd(&a.dev->n_blend, v[1]);
+      atomicAdd(&a.dev->wave_steps, v[2]);
+      atomicAdd(&a.dev->wave_pass, v[3]);
+      atomicAdd(&a.dev->wave_blend, v[4]);
     }
-    __syncthreads();
-    if (tid == 0) {
-      atomicAdd(&a.dev->n_eval, cnt[0]);
-      atomicAdd(&a.dev->n_blend, cnt[1]);
-      atomicAdd(&a.dev->wave_steps, cnt[2]);
-      atomicAdd(&a.dev->wave_pass, cnt[3]);
-      atomicAdd(&a.dev->wave_blend, cnt[4]);
-    }
-  }
-  // the last workgroup out re-arms the queue for the next launch
-  if (tid == 0 && atomicAdd(&a.dev->tile_done, 1) == (int)gridDim.x - 1) {
-    atomicExch(&a.dev->tile_queue, 0);
-    atomicExch(&a.dev->tile_done, 0);
   }
 }
 
@@ -369,10 +336,10 @@ hipError_t launch_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s, bool 
   if (count) {                        // work counts: single renders only
     if (a.table) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(1), 0, s, a.dev);
-    hipLaunchKernelGGL((k_render<C, RENDER_B, true, false>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_render<C, true, false>), dim3(grid), dim3(256), 0, s, a);
   } else {
-    if (a.table) hipLaunchKernelGGL((k_render<C, RENDER_B, false, true>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_render<C, RENDER_B, false, false>), dim3(grid), dim3(256), 0, s, a);
+    if (a.table) hipLaunchKernelGGL((k_render<C, false, true>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_render<C, false, false>), dim3(grid), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -95,6 +95,8 @@ struct Slot {
   uint64_t* keys = nullptr;
   uint64_t* keys_tmp = nullptr;
   int32_t* sorted = nullptr;
+  int2* qlist = nullptr;
+  int32_t* qcount = nullptr;
   float* T_final = nullptr;
   int32_t* last = nullptr;
   float* g2d = nullptr;
@@ -163,7 +165,8 @@ int64_t keys_est(const tg_server* s, int64_t n) {
 int64_t footprint_of(const tg_server* s, const tg_request& r) {
   const int64_t px = (int64_t)r.cam.width * r.cam.height;
   const int64_t per_g = r.d_feat ? 76 + 24 : 76;
-  return tg::padded(r.g.n) * per_g + keys_est(s, r.g.n) * 20 + px * (8 + 4 * ((int64_t)s->opts.c + 1));
+  // per key: key, scratch key, sorted index and room for four quadrant entries (52 B)
+  return tg::padded(r.g.n) * per_g + keys_est(s, r.g.n) * 52 + px * (8 + 4 * ((int64_t)s->opts.c + 1));
 }
 
 // Clear the per-batch device flags.
@@ -212,6 +215,8 @@ tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
   b.keys = sl.keys;
   b.keys_tmp = sl.keys_tmp;
   b.sorted = sl.sorted;
+  b.qlist = sl.qlist;
+  b.qcount = sl.qcount;
   b.g2d = sl.g2d;
   b.g_cap = s->cap_gauss;
   b.key_cap = s->cap_keys;
@@ -264,7 +269,8 @@ void free_slot(Slot& sl) {
   if (sl.graph_fb) (void)hipGraphDestroy(sl.graph_fb);
   void* d[] = {sl.xy, sl.conic_o, sl.wq, sl.ext, sl.rect, sl.depth, sl.tile_count, sl.tile_start, sl.tile_cursor,
                sl.tile_order,
-               sl.keys, sl.keys_tmp, sl.sorted, sl.T_final, sl.last, sl.g2d, sl.dev, sl.table_dev,
+               sl.keys, sl.keys_tmp, sl.sorted, sl.qlist, sl.qcount, sl.T_final, sl.last, sl.g2d, sl.dev,
+               sl.table_dev,
                sl.hdr_dev};
   for (void* p : d)
     if (p) (void)hipFree(p);
@@ -286,6 +292,7 @@ bool alloc_slot(tg_server* s, Slot& sl) {
             dalloc(&sl.tile_count, t) && dalloc(&sl.tile_start, t + 1) && dalloc(&sl.tile_cursor, t) &&
             dalloc(&sl.tile_order, t) &&
             dalloc(&sl.keys, k) && dalloc(&sl.keys_tmp, k) && dalloc(&sl.sorted, k) &&
+            dalloc(&sl.qlist, 4 * k) && dalloc(&sl.qcount, 4 * t) &&
             dalloc(&sl.T_final, px) && dalloc(&sl.last, px) &&
             dalloc(&sl.g2d, s->opts.backward ? 6 * g : 1) && dalloc(&sl.dev, 1) &&
             dalloc(&sl.table_dev, tg::MAX_BATCH) && dalloc(&sl.hdr_dev, 1) &&
@@ -503,7 +510,8 @@ tg_status tg_serve_create(tg_ctx* ctx, const tg_serve_opts* opts, tg_server** ou
       o.max_pixels_per_batch < 1 || o.max_side < 1 || o.max_side > 65535 * tg::TILE || o.budget_bytes <= 0 ||
       !(o.c == 8 || o.c == 16 || o.c == 32 || o.c == 64) || !(o.keys_per_gaussian > 0.f) ||
       o.batch_window_us < 0 || o.batch_window_us > 1000000 || (o.backward != 0 && o.backward != 1) ||
-      o.max_gauss_per_batch >= ((int64_t)1 << 31))
+      o.max_gauss_per_batch >= tg::MAX_GAUSS_SPACE ||
+      tg::padded(o.max_gauss_per_batch) + (int64_t)o.max_batch * tg::BIN_CHUNK > tg::MAX_GAUSS_SPACE)
     return TG_ERR_INVALID;
   const int device = tg::ctx_device(ctx);
   if (hipSetDevice(device) != hipSuccess) return TG_ERR_HIP;

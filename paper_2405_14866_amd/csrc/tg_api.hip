@@ -33,6 +33,8 @@ struct tg_frame {
   uint64_t* keys = nullptr;
   uint64_t* keys_tmp = nullptr;
   int32_t* sorted = nullptr;
+  int2* qlist = nullptr;
+  int32_t* qcount = nullptr;
   float* T_final = nullptr;
   int32_t* last = nullptr;
   float* g2d = nullptr;          // [6][g_cap] backward accumulators
@@ -106,7 +108,7 @@ tg_status dalloc(T** p, size_t count) {
 
 void free_frame(tg_frame* f) {
   void* ptrs[] = {f->xy, f->conic_o, f->wq, f->ext, f->rect, f->depth, f->tile_count, f->tile_start,
-                  f->tile_cursor, f->tile_order, f->keys, f->keys_tmp, f->sorted, f->T_final,
+                  f->tile_cursor, f->tile_order, f->keys, f->keys_tmp, f->sorted, f->qlist, f->qcount, f->T_final,
                   f->last, f->g2d, f->dev, f->table_dev, f->hdr_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -150,6 +152,8 @@ tg::BatchArgs frame_args(tg_frame* f) {
   b.keys = f->keys;
   b.keys_tmp = f->keys_tmp;
   b.sorted = f->sorted;
+  b.qlist = f->qlist;
+  b.qcount = f->qcount;
   b.g2d = f->g2d;
   b.g_cap = f->g_cap;
   b.key_cap = f->max_keys;
@@ -243,7 +247,7 @@ tg_status tg_frame_create_views(tg_ctx* ctx, int32_t max_views, int64_t max_n, i
   f->max_w = max_w;
   f->max_h = max_h;
   const int64_t tx = (max_w + tg::TILE - 1) / tg::TILE, ty = (max_h + tg::TILE - 1) / tg::TILE;
-  if (tx * ty * max_views >= ((int64_t)1 << 31) || tg::padded(max_n > 0 ? max_n : 1) * max_views >= ((int64_t)1 << 31)) {
+  if (tx * ty * max_views >= ((int64_t)1 << 31) || tg::padded(max_n > 0 ? max_n : 1) * max_views > tg::MAX_GAUSS_SPACE) {
     delete f;
     return TG_ERR_INVALID;
   }
@@ -266,6 +270,8 @@ tg_status tg_frame_create_views(tg_ctx* ctx, int32_t max_views, int64_t max_n, i
   if (st == TG_OK) st = dalloc(&f->keys, max_keys);
   if (st == TG_OK) st = dalloc(&f->keys_tmp, max_keys);
   if (st == TG_OK) st = dalloc(&f->sorted, max_keys);
+  if (st == TG_OK) st = dalloc(&f->qlist, 4 * (size_t)max_keys);
+  if (st == TG_OK) st = dalloc(&f->qcount, 4 * (size_t)f->max_tiles);
   if (st == TG_OK) st = dalloc(&f->T_final, npix);
   if (st == TG_OK) st = dalloc(&f->last, npix);
   if (st == TG_OK) st = dalloc(&f->g2d, (size_t)6 * f->g_cap);

@@ -35,6 +35,12 @@
 //   per key       keys    uint64   (depth << 32) | global index, grouped by tile
 //                 keys_tmp uint64  scratch for segments too long for LDS
 //                 sorted  int32    global index, per tile in (depth, index) order
+//                 qlist   int2     (global index, position in the tile's list) of the
+//                                  entries whose alpha support reaches each 8x8
+//                                  quadrant, in list order: tile t with segment
+//                                  [s, s + n) keeps quadrant q's list at
+//                                  qlist[4 s + q n ...] (room for 4 keys per key),
+//                                  its length at qcount[4 t + q]
 //   per pixel     T_final float32, last int32 (read by the backward pass),
 //                 one slice per request
 //   device state  FrameDev (overflow flag, key count, work queue, counters)
@@ -49,11 +55,12 @@ constexpr int TILE = 16;
 constexpr int BIN_LDS_MAX_TILES = 32768;  // per-tile counters kept in LDS (128 KB)
 constexpr int BIN_CHUNK = 1024;           // Gaussians per binning workgroup (and index alignment)
 constexpr int MAX_BATCH = 64;             // requests per batch
+// Gaussian indices of a frame or batch (the padded index space) stay below
+// this: the binning packs a 4-bit quadrant mask above the index in a key.
+constexpr int64_t MAX_GAUSS_SPACE = (int64_t)1 << 28;
 
 struct FrameDev {
   int32_t overflow;             // set when the binning needs more keys than the frame holds
-  int32_t tile_queue;           // next tile of the persistent forward loop
-  int32_t tile_done;            // forward workgroups finished (the last one resets both)
   int32_t bwd_queue;            // next tile of the persistent backward loop
   int32_t bwd_done;             // backward workgroups finished (the last one resets both)
   int32_t pad;
@@ -138,6 +145,8 @@ struct BatchArgs {
   uint64_t* keys;
   uint64_t* keys_tmp;
   int32_t* sorted;
+  int2* qlist;           // [4 key_cap] quadrant lists
+  int32_t* qcount;       // [4 tiles] quadrant list lengths
   float* g2d;            // [6][g_cap]
   int64_t g_cap;         // capacity of the global Gaussian index space
   int64_t key_cap;

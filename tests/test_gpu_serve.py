@@ -150,7 +150,7 @@ def test_budget_and_capacity():
     # a budget that holds the largest request alone: everything still completes, and
     # the requests in flight at any moment never exceed it (bytes a request occupies
     # in flight: padded state, estimated keys, pixel state and outputs)
-    fp = lambda sc: (-(-sc.n // 1024) * 1024) * 76 + (int(sc.n * 5.0) + 1024) * 20 + \
+    fp = lambda sc: (-(-sc.n // 1024) * 1024) * 76 + (int(sc.n * 5.0) + 1024) * 52 + \
         sc.cam.width * sc.cam.height * (8 + 4 * 33)
     budget = max(fp(sc) for sc in reqs)
     srv = Server(0, c=32, slots=2, max_batch=4, max_gauss_per_batch=60000, max_keys_per_batch=600000,
