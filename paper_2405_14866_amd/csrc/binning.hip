@@ -174,74 +174,193 @@ __device__ __forceinline__ T wave_incl_scan(T x, int lane) {
   return x;
 }
 
-// The scan of one workgroup over the tile counts, each lane owning PER
-// consecutive tiles; when PER is a compile-time bound the lane's counts are
-// read once into registers (all loads in flight together).
-template <int KMAX>
-__device__ __forceinline__ void scan_tiles(const BatchArgs& a, int nt, int per, int64_t* wsum, int32_t* bucket) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int b = min(nt, tid * per), e = min(nt, b + per);
-  const int m = e - b;
-  int32_t cnt[KMAX > 0 ? KMAX : 1];
-  auto count = [&](int k) -> int32_t { return KMAX > 0 ? cnt[k] : a.tile_count[b + k]; };
-  if constexpr (KMAX > 0) {
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) cnt[k] = k < m ? a.tile_count[b + k] : 0;
-  }
-  const int mm = KMAX > 0 ? KMAX : m;         // loop bound (the cached counts beyond m are zero)
-  int64_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < mm; ++k) if (k < m) sum += count(k);
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// The scan of one workgroup over the tile counts.  Empty tiles -- most of
+// a frame's, all in the last order bucket -- are counted and placed with one
+// LDS atomic per wave (a ballot), since per-lane atomics on one LDS word
+// serialise; the other tiles spread over the buckets and take one atomic
+// each.  Positions inside a bucket are taken in arrival order; the blend of
+// a tile does not depend on when it runs.
+struct ScanShared {
+  int64_t wsum[16];
+  int32_t bucket[ORDER_BUCKETS];
+};
+
+__device__ __forceinline__ void count_bucket(int32_t c, bool v, int32_t* bucket, int lane) {
+  const uint64_t empty = __ballot(v && c == 0);
+  if (v && c != 0) atomicAdd(&bucket[order_bucket(c)], 1);
+  if (lane == 0 && empty) atomicAdd(&bucket[ORDER_BUCKETS - 1], __popcll(empty));
+}
+
+__device__ __forceinline__ void place_tile(const BatchArgs& a, int32_t c, bool v, int t, int32_t* bucket, int lane,
+                                           uint64_t below) {
+  const uint64_t empty = __ballot(v && c == 0);
+  int pos = 0;
+  if (v && c != 0) pos = atomicAdd(&bucket[order_bucket(c)], 1);
+  int e0 = 0;
+  if (lane == 0 && empty) e0 = atomicAdd(&bucket[ORDER_BUCKETS - 1], __popcll(empty));
+  e0 = __shfl(e0, 0, 64);
+  if (v && c == 0) pos = e0 + __popcll(empty & below);
+  if (v) a.tile_order[pos] = t;
+}
+
+// Exclusive scan of one sweep's lane sums over the workgroup: the lane's
+// start (plus carry) and the sweep's total.
+__device__ __forceinline__ void block_scan(int64_t sum, int64_t carry, ScanShared& sh, int64_t& run, int64_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t incl = wave_incl_scan(sum, lane);
-  if (lane == 63) wsum[wv] = incl;
+  if (lane == 63) sh.wsum[wv] = incl;
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < mm; ++k) if (k < m) atomicAdd(&bucket[order_bucket(count(k))], 1);
-  int64_t run = incl - sum, total = 0;
+  run = carry + incl - sum;
+  total = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const int64_t v = wsum[k];
+    const int64_t v = sh.wsum[k];
     run += k < wv ? v : 0;
     total += v;
   }
+}
+
+__device__ __forceinline__ void write_start(const BatchArgs& a, int t, int32_t v) {
+  a.tile_start[t] = v;
+  a.tile_cursor[t] = v;
+  // quadrant list lengths: the sort sets those of non-empty tiles
+  reinterpret_cast<int4*>(a.qcount)[t] = make_int4(0, 0, 0, 0);
+}
+
+// Key total, overflow flag and, on overflow, empty segments everywhere.
+__device__ __forceinline__ bool finish_scan(const BatchArgs& a, int nt, int64_t total) {
   const bool over = total > a.key_cap;
-#pragma unroll
-  for (int k = 0; k < mm; ++k) {
-    if (k < m) {
-      const int32_t v = over ? 0 : (int32_t)run;
-      a.tile_start[b + k] = v;
-      a.tile_cursor[b + k] = v;
-      // quadrant list lengths: the sort sets those of non-empty tiles
-      reinterpret_cast<int4*>(a.qcount)[b + k] = make_int4(0, 0, 0, 0);
-      run += count(k);
+  if (over)
+    for (int t = threadIdx.x; t < nt; t += 1024) {
+      a.tile_start[t] = 0;
+      a.tile_cursor[t] = 0;
     }
-  }
-  if (tid == 1023) {
+  if (threadIdx.x == 0) {
     a.tile_start[nt] = over ? 0 : (int32_t)total;
     a.dev->n_keys = total;
     a.dev->overflow = over ? 1 : 0;
   }
+  return over;
+}
+
+__device__ __forceinline__ void bucket_starts(ScanShared& sh) {
   __syncthreads();
-  if (tid < ORDER_BUCKETS) {                    // bucket sizes -> first positions
-    const int32_t c = bucket[tid];
-    bucket[tid] = wave_incl_scan(c, lane) - c;
+  if (threadIdx.x < ORDER_BUCKETS) {             // bucket sizes -> first positions
+    const int32_t c = sh.bucket[threadIdx.x];
+    sh.bucket[threadIdx.x] = wave_incl_scan(c, (int)threadIdx.x) - c;
   }
   __syncthreads();
-  // positions inside a bucket are taken in arrival order; the blend of a
-  // tile does not depend on when it runs
+}
+
+// Up to 8 tiles per lane (8,192 tiles): lane i owns tiles [8 i, 8 i + 8) and
+// keeps their counts in registers, all loads in flight together.
+constexpr int SCAN_REG = 8;
+
+__device__ __forceinline__ void scan_small(const BatchArgs& a, int nt, int per, ScanShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int b = min(nt, tid * per), m = min(nt, b + per) - b;
+  int32_t cnt[SCAN_REG];
 #pragma unroll
-  for (int k = 0; k < mm; ++k)
-    if (k < m) a.tile_order[atomicAdd(&bucket[order_bucket(count(k))], 1)] = b + k;
+  for (int k = 0; k < SCAN_REG; ++k) cnt[k] = k < m ? a.tile_count[b + k] : 0;
+  int64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_REG; ++k) {
+    sum += cnt[k];
+    count_bucket(cnt[k], k < m, sh.bucket, lane);
+  }
+  int64_t run, total;
+  block_scan(sum, 0, sh, run, total);
+  if (!(total > a.key_cap)) {
+#pragma unroll
+    for (int k = 0; k < SCAN_REG; ++k)
+      if (k < m) {
+        write_start(a, b + k, (int32_t)run);
+        run += cnt[k];
+      }
+  } else {
+#pragma unroll
+    for (int k = 0; k < SCAN_REG; ++k)
+      if (k < m) reinterpret_cast<int4*>(a.qcount)[b + k] = make_int4(0, 0, 0, 0);
+  }
+  finish_scan(a, nt, total);
+  bucket_starts(sh);
+  const uint64_t below = lanes_below();
+#pragma unroll
+  for (int k = 0; k < SCAN_REG; ++k) place_tile(a, cnt[k], k < m, b + k, sh.bucket, lane, below);
+}
+
+// More tiles (batches): chunks of SCAN_CHUNK tiles staged in LDS by
+// coalesced loads (all of a lane's in flight together), lane i owning the
+// SCAN_PER consecutive tiles [i SCAN_PER, (i + 1) SCAN_PER) of a chunk
+// (rows padded by one word against bank conflicts).  A first sweep writes
+// the starts (carried across chunks) and counts the buckets, a second
+// places the tiles.
+constexpr int SCAN_PER = 16;
+constexpr int SCAN_CHUNK = 1024 * SCAN_PER;
+
+__device__ __forceinline__ int scan_slot(int j) { return (j / SCAN_PER) * (SCAN_PER + 1) + j % SCAN_PER; }
+
+__device__ __forceinline__ void load_chunk(const BatchArgs& a, int c0, int nt, int32_t* cnt) {
+  int32_t v[SCAN_PER];
+  const int n = min(nt - c0, SCAN_CHUNK);
+#pragma unroll
+  for (int i = 0; i < SCAN_PER; ++i) {
+    const int j = (int)threadIdx.x + 1024 * i;
+    v[i] = j < n ? a.tile_count[c0 + j] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < SCAN_PER; ++i) cnt[scan_slot((int)threadIdx.x + 1024 * i)] = v[i];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void scan_large(const BatchArgs& a, int nt, ScanShared& sh, int32_t* cnt) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int32_t* my = cnt + tid * (SCAN_PER + 1);
+  int64_t carry = 0;
+  for (int c0 = 0; c0 < nt; c0 += SCAN_CHUNK) {
+    load_chunk(a, c0, nt, cnt);
+    const int b = c0 + tid * SCAN_PER;
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) {
+      sum += my[k];
+      count_bucket(my[k], b + k < nt, sh.bucket, lane);
+    }
+    int64_t run, total;
+    block_scan(sum, carry, sh, run, total);
+    for (int k = 0; k < SCAN_PER && b + k < nt; ++k) {
+      write_start(a, b + k, (int32_t)run);   // an overflow zeroes the starts again
+      run += my[k];
+    }
+    carry += total;
+    __syncthreads();                          // wsum and the chunk's counts are reused
+  }
+  finish_scan(a, nt, carry);
+  bucket_starts(sh);
+  const uint64_t below = lanes_below();
+  for (int c0 = 0; c0 < nt; c0 += SCAN_CHUNK) {
+    load_chunk(a, c0, nt, cnt);
+    const int b = c0 + tid * SCAN_PER;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) place_tile(a, my[k], b + k < nt, b + k, sh.bucket, lane, below);
+    __syncthreads();                          // the chunk's counts are reused
+  }
 }
 
 __global__ void __launch_bounds__(1024) k_scan(BatchArgs a) {
-  __shared__ int64_t wsum[16];
-  __shared__ int32_t bucket[ORDER_BUCKETS];
+  __shared__ ScanShared sh;
+  __shared__ int32_t cnt[1024 * (SCAN_PER + 1)];
   const int nt = batch_hdr(a).n_tiles;
+  if (threadIdx.x < ORDER_BUCKETS) sh.bucket[threadIdx.x] = 0;
+  __syncthreads();
   const int per = (nt + 1023) / 1024;
-  if (threadIdx.x < ORDER_BUCKETS) bucket[threadIdx.x] = 0;
-  if (per <= 8) scan_tiles<8>(a, nt, per, wsum, bucket);
-  else scan_tiles<0>(a, nt, per, wsum, bucket);
+  if (per <= SCAN_REG) scan_small(a, nt, per, sh);
+  else scan_large(a, nt, sh, cnt);
 }
 
 // Scatter of one chunk's keys into the tile segments: LDS counts, one

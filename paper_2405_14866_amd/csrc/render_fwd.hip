@@ -14,20 +14,24 @@
 //   * the quadrant list is consumed in batches of B entries (B = 24 at
 //     C = 32: two 3 KB feature buffers per wave, five 4-wave workgroups per
 //     CU): while batch b is walked, batch b+1's feature rows arrive in the
-//     wave's other LDS buffer by LDS DMA (global_load_lds_dwordx4, C/4 lanes
-//     per row), its FP64 mean and exponent factors and the entries of batch
-//     b+2 load into registers; after the walk batch b+1's tile-dependent
-//     offsets are formed and staged in the wave's LDS, and the wave waits
-//     for its own DMA only;
+//     wave's other LDS buffer and its FP64 means and exponent factors in the
+//     wave's raw slots, all by LDS DMA (global_load_lds_dwordx4, C/4 lanes
+//     per feature row), so no register is held for them across the walk;
+//     the entries of batch b+2 load into a register.  After the walk the
+//     wave waits for its own DMA, forms batch b+1's tile-dependent offsets
+//     and stages them;
+//   * the work item, and so the tile, its request and its lists, is
+//     wave-uniform and kept in scalar registers;
 //   * per staged Gaussian the walk reads the projection's exponent factors
 //     (s, s k, r, log2 o) and the tile-dependent offsets (c1, c2), formed in
 //     FP64 from the FP64 mean relative to the tile origin (so pixel offsets
 //     are accurate to ~1e-7 px); log2 of the opacity-weighted Gaussian at a
 //     pixel is then log2 o - z1^2 - z2^2 with z1, z2 affine in the pixel
 //     centre: five FMAs and one v_exp_f32 give o G;
-//   * the walk takes two entries per iteration: their alphas are
-//     independent and overlap, then their decisions and feature
-//     accumulations run in list order.  A pixel's threshold test is one
+//   * the walk takes two entries per iteration, read at fixed LDS offsets
+//     (the second slot is always inside the batch buffers; past the batch's
+//     end it is masked): their alphas are independent and overlap, then
+//     their decisions and feature accumulations run in list order.  A pixel's threshold test is one
 //     compare against its own minimum alpha (1/255 while it runs, 2 once it
 //     has ended, so an ended pixel fails every later test); the state
 //     updates of a blend and its feature accumulation sit behind a
@@ -86,6 +90,8 @@ struct WaveLDS {
   __align__(16) float fe[2][B * C];  // feature rows, DMA targets
   float4 wq[B];                      // exponent factors
   float4 st[B];                      // (c1, c2, tile-list position as bits, -)
+  double2 rxy[B];                    // next batch's FP64 means, DMA target
+  float4 rwq[B];                     // next batch's exponent factors, DMA target
 };
 
 // Entries per batch: two feature buffers of 3 KB (C >= 16), so that five
@@ -188,29 +194,32 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
     const bool more = b + 1 < nbatch;
     const int nb1 = more ? min(B, qn - b0 - B) : 0;
     float* cur = L.fe[b & 1];
-    // ---- batch b+1: its rows on their way into the other buffer, its
-    // state and the entries of batch b+2 loading into registers
-    double2 nxy = make_double2(0.0, 0.0);
-    float4 nwq = make_float4(0.f, 0.f, 0.f, 0.f);
+    // ---- batch b+1: its rows into the other buffer and its FP64 means and
+    // exponent factors into the wave's raw slots, all by LDS DMA (nothing
+    // held in registers across the walk); the entries of batch b+2 into a
+    // register
     int2 en2 = make_int2(0, 0);
     if (more) {
       dma_rows<C, B>(feat, g_off, L.fe[(b + 1) & 1], en.x, nb1, lane);
       if (lane < nb1) {
-        nxy = a.xy[en.x];
-        nwq = a.wq[en.x];
+        __builtin_amdgcn_global_load_lds((const void*)(a.xy + en.x), (lds_void*)L.rxy, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(a.wq + en.x), (lds_void*)L.rwq, 16, 0, 0);
       }
       if (lane < B && b0 + 2 * B + lane < qn) en2 = ql[b0 + 2 * B + lane];
     }
     // ---- walk batch b, two entries per iteration: their alphas are
-    // independent and overlap; the decisions and accumulations run in list order
+    // independent and overlap; the decisions and accumulations run in list
+    // order.  Slot j + 1 is always inside the batch buffers (B is even), so
+    // both entries are read at fixed offsets with no clamp; past the end of
+    // the batch its contents are stale and has2 keeps them out.
+    static_assert(B % 2 == 0, "entry pairs stay inside the batch buffers");
     for (int j = 0; j < nb; j += 2) {
-      const int j2 = j + 1 < nb ? j + 1 : j;
       const bool has2 = j + 1 < nb;
       float fl1[NM], fl2[NM];
       load_slice<NM>(cur + j * C + NM * q4, fl1);
-      load_slice<NM>(cur + j2 * C + NM * q4, fl2);
-      const float4 w1 = L.wq[j], w2 = L.wq[j2];
-      const float4 s1 = L.st[j], s2 = L.st[j2];
+      load_slice<NM>(cur + (j + 1) * C + NM * q4, fl2);
+      const float4 w1 = L.wq[j], w2 = L.wq[j + 1];
+      const float4 s1 = L.st[j], s2 = L.st[j + 1];
       const float al1 = blend_alpha(exponent(w1, s1.x, s1.y, fpx, fpy));
       const float al2 = blend_alpha(exponent(w2, s2.x, s2.y, fpx, fpy));
       if (COUNT) wc.steps += has2 ? 2 : 1;
@@ -218,15 +227,17 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
       visit(fl2, __float_as_int(s2.z), al2, has2);
     }
     const bool live = __builtin_amdgcn_ballot_w64(amin < 1.f) != 0;
-    // ---- stage batch b+1's state (batch b's is no longer read)
+    // ---- batch b+1 has landed; stage its state (batch b's is no longer read)
+    __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     if (more && lane < nb1) {
+      const double2 nxy = L.rxy[lane];
+      const float4 nwq = L.rwq[lane];
       const float2 cc = exponent_offsets(nxy, nwq, ox, oy);
       L.wq[lane] = nwq;
       L.st[lane] = make_float4(cc.x, cc.y, __int_as_float(en.y), 0.f);
     }
     en = en2;
-    __builtin_amdgcn_s_waitcnt(0);    // batch b+1's rows have landed
     __builtin_amdgcn_wave_barrier();
     if (!live) break;                 // every pixel of the quadrant has ended
   }
@@ -294,10 +305,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
   constexpr int B = wave_batch<C>();
   __shared__ WaveLDS<C, B> LW[4];
   const int lane = threadIdx.x & 63;
-  WaveLDS<C, B>& L = LW[threadIdx.x >> 6];
+  // the wave's index, as a wave-uniform (scalar) value: everything derived
+  // from the work item (tile, request, list bounds) then stays in scalar
+  // registers and scalar arithmetic
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  WaveLDS<C, B>& L = LW[wv];
   WorkCount wc;
   const int n_items = 4 * h.n_tiles;
-  for (int item = 4 * (int)blockIdx.x + (int)(threadIdx.x >> 6); item < n_items; item += 4 * (int)gridDim.x) {
+  for (int item = 4 * (int)blockIdx.x + wv; item < n_items; item += 4 * (int)gridDim.x) {
     const int t = a.tile_order[item >> 2];
     const int r = req_of_tile(a, h, t);
     if (r < 0) break;
