@@ -259,7 +259,7 @@ tg_status tg_render_bwd_views(tg_frame* frame, const tg_gaussians* g, const floa
 #define TG_NOALLOC_MAX_KEYS 2097152
 #define TG_NOALLOC_MAX_PIXELS 1048576
 #define TG_NOALLOC_MAX_TILES 8192
-#define TG_NOALLOC_SCRATCH_BYTES 157549056
+#define TG_NOALLOC_SCRATCH_BYTES 157680128
 tg_status tg_render_noalloc(tg_ctx* ctx, const tg_gaussians* g, const tg_camera* cam, const float* bg,
                             float* out_feat, float* out_alpha, int32_t* status, void* stream);
 

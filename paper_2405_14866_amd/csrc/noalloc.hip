@@ -38,7 +38,7 @@ constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 struct Layout {
   size_t xy, conic_o, wq, ext, rect, depth;
   size_t tile_count, tile_start, tile_cursor, tile_order;
-  size_t keys, keys_tmp, sorted, qlist, qcount;
+  size_t keys, keys_tmp, sorted, qlist, qcount, qcut;
   size_t T_final, last, dev, total;
 };
 
@@ -60,6 +60,7 @@ constexpr Layout make_layout() {
   l.sorted = o;      o += align256(NA_MAX_KEYS * sizeof(int32_t));
   l.qlist = o;       o += align256(4 * NA_MAX_KEYS * sizeof(int2));
   l.qcount = o;      o += align256(4 * NA_MAX_TILES * sizeof(int32_t));
+  l.qcut = o;        o += align256(4 * NA_MAX_TILES * sizeof(int32_t));
   l.T_final = o;     o += align256(NA_MAX_PIXELS * sizeof(float));
   l.last = o;        o += align256(NA_MAX_PIXELS * sizeof(int32_t));
   l.dev = o;         o += align256(sizeof(FrameDev));
@@ -185,6 +186,7 @@ extern "C" tg_status tg_render_noalloc(tg_ctx* ctx, const tg_gaussians* g, const
   a.sorted = at<int32_t>(base, LAYOUT.sorted);
   a.qlist = at<int2>(base, LAYOUT.qlist);
   a.qcount = at<int32_t>(base, LAYOUT.qcount);
+  a.qcut = at<int32_t>(base, LAYOUT.qcut);
   a.g2d = nullptr;                       // forward only: no adjoint accumulators
   a.g_cap = NA_MAX_N;
   a.key_cap = NA_MAX_KEYS;

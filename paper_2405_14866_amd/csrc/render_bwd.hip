@@ -1,9 +1,13 @@
 // render_bwd.hip -- adjoint of the rasterizer (gfx950).  §4.2 trains the
 // encoder and decoder through R_G, so R_G must be differentiable.
 //
-// k_render_bwd: persistent 256-lane workgroups over the tiles (longest
-// first), the forward's pixel layout (wave w owns the 8x8 quadrant
-// (w & 1, w >> 1)).  Nothing per (pixel, Gaussian) is stored by the
+// k_render_bwd: one wave64 per (tile, 8x8 quadrant) work item, the
+// forward's pixel layout and work assignment, walking the quadrant's own
+// list (from the sort) backwards from the end the forward recorded for it
+// (one past the last entry some pixel of the quadrant blended), with no
+// workgroup barrier.  Each group of 16 entries arrives by LDS DMA (feature
+// rows, FP64 means, exponent factors, conics) while the previous group's
+// sums run.  Nothing per (pixel, Gaussian) is stored by the
 // forward: each pixel starts from its final transmittance T_final and the
 // list position of its last blended Gaussian and walks its list backwards,
 // re-deciding skip / blend with the forward's own float operations (shared
@@ -17,9 +21,9 @@
 // and the pixel offset d = p - (u, v).
 //
 // The per-Gaussian sums over a wave's 64 pixels are dense contractions and
-// run on the matrix cores.  Each wave walks the Gaussians that reach its
-// quadrant (the forward's conservative quadrant test) in groups of 16; the
-// walk writes each pixel's w_i and dL/dP_i into LDS, then
+// run on the matrix cores.  Each wave walks the Gaussians of its quadrant
+// list in groups of 16; the walk writes each pixel's w_i and dL/dP_i into
+// LDS, then
 //   dL/df[i][c]  = sum_p w_i(p) g(p)[c]            (16 x C x 64)
 //   M[i][k]      = sum_p dL/dP_i(p) phi_k(p)         (16 x 6 x 64)
 // are v_mfma_f32_16x16x4_f32 products with the pixels as the reduction
@@ -36,33 +40,43 @@
 namespace tg {
 namespace {
 
-constexpr int BWD_B = 64;      // Gaussians per staged batch
-constexpr int GROUP = 16;      // Gaussians per matrix-core reduction
+constexpr int GROUP = 16;      // Gaussians per staged group and per matrix-core reduction
 // LDS row of one group Gaussian's 64 pixel values, padded by 4 floats: the
 // matrix-core operand reads take one row per lane column (16 rows at once),
 // and an unpadded 64-float stride would put all of them on the same banks
 constexpr int ROW = 68;
 
+// One wave's LDS (four per workgroup, nothing shared): the feature rows of
+// the group being walked (LDS DMA target, refilled with the next group's
+// while this group's sums run), the next group's raw FP64 means, exponent
+// factors and conics (DMA targets), this group's staged state in walk order,
+// and the pixel values of the matrix-core sums.  The DMA targets are the
+// wave's rows of LDS arrays of their own, so the compiler can tell them from
+// what the sums and the atomics read: those never wait for the DMA.
+struct BwdBufs {
+  float* fe;                   // [GROUP * C] feature rows
+  double2* rxy;                // [GROUP] raw FP64 means
+  float4* rwq;                 // [GROUP] raw exponent factors
+  float4* rcn;                 // [GROUP] raw conics and opacities
+};
+
 template <int C>
-struct BwdShared {
-  float4 wq[BWD_B];            // exponent factors, as in the forward
-  float4 st[BWD_B];            // (c1, c2, u, v): tile offsets and tile-relative mean
-  float4 cn[BWD_B];            // unscaled conic A, B, C and opacity
-  uint32_t qm[BWD_B];          // quadrant masks
-  int32_t sidx[BWD_B];
-  __align__(16) float fe[BWD_B * C];
-  int32_t wl[4][BWD_B];        // per wave: reaching batch entries, last first
-  // per wave, row i of the group: pixel values in k-block order, p = 4 kb + q
-  // stored at q * 16 + kb (so one lane's 16 A operands are contiguous)
-  __align__(16) float wa[4][GROUP * ROW];
-  __align__(16) float dp[4][GROUP * ROW];
-  float mom[4][GROUP][9];      // 9: rows on distinct banks for the per-row reads
-  int32_t smax;
+struct BwdWork {
+  float4 wq[GROUP];            // exponent factors, as in the forward
+  float4 st[GROUP];            // (c1, c2, u, v): tile offsets and tile-relative mean
+  float4 cn[GROUP];            // unscaled conic A, B, C and opacity
+  int2 ent[GROUP];             // (global index, tile-list position)
+  // row i of the group: pixel values in k-block order, p = 4 kb + q stored at
+  // q * 16 + kb (so one lane's 16 A operands are contiguous)
+  __align__(16) float wa[GROUP * ROW];
+  __align__(16) float dp[GROUP * ROW];
+  float mom[GROUP][9];         // 9: rows on distinct banks for the per-row reads
 };
 
 __device__ __forceinline__ int perm64(int p) { return (p & 3) * 16 + (p >> 2); }
 
 typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(3))) void lds_void;
 
 // float atomic add on a global-memory address (no-return form; the generic
 // form would be a flat atomic that also counts against the LDS counter)
@@ -70,22 +84,75 @@ __device__ __forceinline__ void atomic_add_global(float* p, float v) {
   (void)__builtin_amdgcn_global_atomic_fadd_f32((gfloat*)p, v);
 }
 
+// LDS DMA of a group's feature rows (lane j < n holds entry j's global index
+// gi) and raw state into the wave's buffers: 16-byte chunks, C / 4 lanes per
+// row; lanes past the group's GROUP rows stay idle, rows past n read row 0's
+// address (in bounds) and are never walked.
 template <int C>
-__device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, int gtile, int tx, int ty,
-                                         BwdShared<C>& sh) {
+__device__ __forceinline__ void dma_group(const BatchArgs& a, const float* __restrict__ feat, int64_t g_off,
+                                          const BwdBufs& B, int gi, int n, int lane) {
+  constexpr int LPR = C / 4;
+  constexpr int RPI = 64 / LPR;
+  constexpr int NI = (GROUP + RPI - 1) / RPI;
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const int row = k * RPI + lane / LPR;
+    const int g = __shfl(gi, row < n ? row : 0, 64);
+    if (k * RPI < n && row < GROUP)
+      __builtin_amdgcn_global_load_lds((const void*)(feat + (g - g_off) * C + 4 * (lane % LPR)),
+                                       (lds_void*)(B.fe + k * RPI * C), 16, 0, 0);
+  }
+  if (lane < n) {
+    __builtin_amdgcn_global_load_lds((const void*)(a.xy + gi), (lds_void*)B.rxy, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(a.wq + gi), (lds_void*)B.rwq, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(a.conic_o + gi), (lds_void*)B.rcn, 16, 0, 0);
+  }
+}
+
+// Staged state of group entry j (after its DMA landed): the forward's
+// tile-dependent exponent offsets (the same operations) and the
+// tile-relative mean for the 2D gradient moments.
+template <int C>
+__device__ __forceinline__ void stage_entry(const BwdBufs& B, BwdWork<C>& L, int j, int2 e, double ox, double oy) {
+  const double2 xy = B.rxy[j];
+  const float4 wq = B.rwq[j];
+  const float2 cc = exponent_offsets(xy, wq, ox, oy);
+  L.wq[j] = wq;
+  L.st[j] = make_float4(cc.x, cc.y, (float)(xy.x - ox), (float)(xy.y - oy));
+  L.cn[j] = B.rcn[j];
+  L.ent[j] = e;
+}
+
+// The adjoint of the 8x8 quadrant qd of one tile (tile-local coordinates
+// tx, ty of request q) by one wave: the quadrant's list backwards from the
+// last entry the forward blended in it, in groups of GROUP.
+template <int C>
+__device__ __forceinline__ void bwd_quadrant(const BatchArgs& a, const ReqDev& q, int gtile, int tx, int ty, int qd,
+                                             const BwdBufs& B, BwdWork<C>& L) {
+  const int kend = a.qcut[4 * gtile + qd];
+  if (kend == 0) return;                      // no pixel of the quadrant blended anything
   constexpr int NB = (C + 15) / 16;           // 16-channel blocks of dL/df
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int ql = lane >> 4, l16 = lane & 15;  // MFMA operand row / column of this lane
-  const int qx0 = (w & 1) << 3, qy0 = (w >> 1) << 3;
+  const int lane = threadIdx.x & 63;
+  const int ql4 = lane >> 4, l16 = lane & 15; // MFMA operand row / column of this lane
+  const int qx0 = (qd & 1) << 3, qy0 = (qd >> 1) << 3;
   const int lx = qx0 | (lane & 7), ly = qy0 | (lane >> 3);
   const int W = q.cam.W, H = q.cam.H;
   const int px = tx * TILE + lx, py = ty * TILE + ly;
   const bool inside = px < W && py < H;
   const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
   const double ox = (double)(tx * TILE), oy = (double)(ty * TILE);
-  const int s = a.tile_start[gtile];
-  const uint32_t qbit = 1u << w;
+  const int s = a.tile_start[gtile], len = a.tile_start[gtile + 1] - s;
+  const int2* qlst = a.qlist + 4 * (int64_t)s + (int64_t)qd * len;
   const size_t HW = (size_t)W * H;
+  const float* feat = q.feat;
+  float* const d_feat = q.d_feat;
+  const int64_t g_off = q.s_off;              // the lists hold indices of this 2D-state range
+  const int64_t acc_off = q.g_off - q.s_off;  // ... the adjoint accumulates in the request's own range
+
+  // group 0 (the last GROUP entries) on its way while the pixel state loads
+  int n = min(GROUP, kend);
+  int2 e = lane < n ? qlst[kend - 1 - lane] : make_int2(0, 0);
+  dma_group<C>(a, feat, g_off, B, e.x, n, lane);
 
   // ---- per-pixel state
   float g[C];
@@ -108,13 +175,13 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
 #pragma unroll
     for (int c = 0; c < C; ++c) g[c] = 0.f;
   }
-  // ---- matrix-core operands fixed for the tile.  B of the dL/df product:
-  // lane (ql, l16) of k-block kb holds g[c = 16 nb + l16] of wave pixel
-  // p = 4 kb + ql; B of the moment product holds phi_l16 of that pixel.
+  // ---- matrix-core operands fixed for the quadrant.  B of the dL/df
+  // product: lane (ql4, l16) of k-block kb holds g[c = 16 nb + l16] of wave
+  // pixel p = 4 kb + ql4; B of the moment product holds phi_l16 of that pixel.
   float gB[NB][16], phB[16];
 #pragma unroll
   for (int kb = 0; kb < 16; ++kb) {
-    const int p = 4 * kb + ql;
+    const int p = 4 * kb + ql4;
     const int plx = qx0 | (p & 7), ply = qy0 | (p >> 3);
     const int ppx = tx * TILE + plx, ppy = ty * TILE + ply;
     const bool pin = ppx < W && ppy < H;
@@ -134,108 +201,76 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
     ph = l16 == 5 ? y * y : ph;
     phB[kb] = ph;
   }
-  // ---- the list range any pixel of the tile (of this wave) still needs
-  int wmax = last;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
-  if (tid == 0) sh.smax = -1;
-  __syncthreads();
-  if (lane == 0) atomicMax(&sh.smax, wmax);
-  __syncthreads();
-  const int tmax = sh.smax;
+  __builtin_amdgcn_s_waitcnt(0);              // group 0 has landed
+  __builtin_amdgcn_wave_barrier();
+  if (lane < n) stage_entry<C>(B, L, lane, e, ox, oy);
+  __builtin_amdgcn_wave_barrier();
 
-  float* const d_feat = q.d_feat;
-  const int64_t g_off = q.s_off;              // the list holds indices of this 2D-state range
-  const int64_t acc_off = q.g_off - q.s_off;  // ... the adjoint accumulates in the request's own range
-  for (int b = tmax >= 0 ? tmax / BWD_B : -1; b >= 0; --b) {
-    const int b0 = b * BWD_B;
-    const int nb = min(BWD_B, tmax + 1 - b0);
-    __syncthreads();                          // the previous batch is done with the buffers
-    if (tid < nb) {
-      const int gi = a.sorted[s + b0 + tid];
-      const float4 wq = a.wq[gi];
-      const TileState ts = make_state(a.xy[gi], wq, a.ext[gi], ox, oy);
-      sh.wq[tid] = wq;
-      sh.st[tid] = make_float4(ts.c1, ts.c2, ts.u, ts.v);
-      sh.qm[tid] = ts.mask;
-      sh.cn[tid] = a.conic_o[gi];
-      sh.sidx[tid] = gi;
-    }
-    for (int k = tid; k < nb * (C / 4); k += 256) {
-      const int r = k / (C / 4), c4 = k % (C / 4);
-      const int gi = a.sorted[s + b0 + r];
-      reinterpret_cast<float4*>(sh.fe)[k] =
-          reinterpret_cast<const float4*>(q.feat + (size_t)(gi - g_off) * C)[c4];
-    }
-    __syncthreads();
-    if (b0 > wmax) continue;                  // no pixel of this quadrant reaches this batch
-    // reaching entries of the batch, last first
-    const bool reach = lane < nb && (sh.qm[lane] & qbit) != 0 && b0 + lane <= wmax;
-    const uint64_t mask = __builtin_amdgcn_ballot_w64(reach);
-    const int cnt = __builtin_popcountll(mask);
-    if (reach) sh.wl[w][__builtin_popcountll(lane == 63 ? 0ull : mask >> (lane + 1))] = lane;
-    __builtin_amdgcn_wave_barrier();
-    for (int g0 = 0; g0 < cnt; g0 += GROUP) {
-      const int n = min(GROUP, cnt - g0);
-      uint32_t cmask = 0;                     // rows of the group some pixel blends
-      for (int i = 0; i < n; ++i) {
-        const int j = sh.wl[w][g0 + i];
-        const int pos = b0 + j;
-        const float4 wq = sh.wq[j], st = sh.st[j];
-        const float oG = __builtin_amdgcn_exp2f(exponent(wq, st.x, st.y, fpx, fpy));
-        const float al = fminf(0.99f, oG);
-        const bool contrib = pos <= last && al >= ALPHA_MIN;
-        float wv = 0.f, dv = 0.f;
-        {
-          if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
-            cmask |= 1u << i;
-            const float* fr = sh.fe + j * C;
-            float fg = 0.f;
+  for (int k1 = kend; k1 > 0; k1 -= GROUP) {
+    n = min(GROUP, k1);
+    const int nn = min(GROUP, k1 - GROUP);    // the next group's size (<= 0: none)
+    int2 en = make_int2(0, 0);
+    if (lane < nn) en = qlst[k1 - GROUP - 1 - lane];
+    // ---- walk the group, last entry first: row i is list entry k1 - 1 - i
+    uint32_t cmask = 0;                       // rows of the group some pixel blends
+    for (int i = 0; i < n; ++i) {
+      const int pos = L.ent[i].y;
+      const float4 wq = L.wq[i], st = L.st[i];
+      const float oG = __builtin_amdgcn_exp2f(exponent(wq, st.x, st.y, fpx, fpy));
+      const float al = fminf(0.99f, oG);
+      const bool contrib = pos <= last && al >= ALPHA_MIN;
+      float wv = 0.f, dv = 0.f;
+      if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
+        cmask |= 1u << i;
+        const float* fr = B.fe + i * C;
+        float fg = 0.f;
 #pragma unroll
-            for (int c = 0; c < C; ++c) fg = __builtin_fmaf(fr[c], g[c], fg);
-            // T_i = T_{i+1} / (1 - alpha_i) with a correctly rounded division:
-            // the recursion runs over the whole list, an approximate
-            // reciprocal would let its error grow with the list length
-            const float oma = 1.f - al;
-            const float Ti = T / oma;
-            const float dLda = Ti * fg + (gAT - sgS) * __builtin_amdgcn_rcpf(oma);
-            const float wgt = al * Ti;
-            wv = contrib ? wgt : 0.f;
-            dv = contrib && oG <= 0.99f ? dLda * al : 0.f;
-            sgS = contrib ? __builtin_fmaf(wgt, fg, sgS) : sgS;
-            T = contrib ? Ti : T;
-          }
-        }
-        sh.wa[w][i * ROW + perm64(lane)] = wv;
-        sh.dp[w][i * ROW + perm64(lane)] = dv;
+        for (int c = 0; c < C; ++c) fg = __builtin_fmaf(fr[c], g[c], fg);
+        // T_i = T_{i+1} / (1 - alpha_i) with a correctly rounded division:
+        // the recursion runs over the whole list, an approximate
+        // reciprocal would let its error grow with the list length
+        const float oma = 1.f - al;
+        const float Ti = T / oma;
+        const float dLda = Ti * fg + (gAT - sgS) * __builtin_amdgcn_rcpf(oma);
+        const float wgt = al * Ti;
+        wv = contrib ? wgt : 0.f;
+        dv = contrib && oG <= 0.99f ? dLda * al : 0.f;
+        sgS = contrib ? __builtin_fmaf(wgt, fg, sgS) : sgS;
+        T = contrib ? Ti : T;
       }
-      if (cmask == 0) continue;
-      __builtin_amdgcn_wave_barrier();
-      // ---- sums over the wave's pixels on the matrix cores
+      L.wa[i * ROW + perm64(lane)] = wv;
+      L.dp[i * ROW + perm64(lane)] = dv;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // ---- the feature rows are read: the next group's rows and raw state
+    // arrive by DMA while this group's sums run
+    if (nn > 0) dma_group<C>(a, feat, g_off, B, en.x, nn, lane);
+    if (cmask != 0) {
+      // sums over the wave's pixels on the matrix cores
       f4v accF[NB], accM = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int nb2 = 0; nb2 < NB; ++nb2) accF[nb2] = f4v{0.f, 0.f, 0.f, 0.f};
-      const f4v* wrow = reinterpret_cast<const f4v*>(&sh.wa[w][l16 * ROW + ql * 16]);
-      const f4v* drow = reinterpret_cast<const f4v*>(&sh.dp[w][l16 * ROW + ql * 16]);
+      const f4v* wrow = reinterpret_cast<const f4v*>(&L.wa[l16 * ROW + ql4 * 16]);
+      const f4v* drow = reinterpret_cast<const f4v*>(&L.dp[l16 * ROW + ql4 * 16]);
 #pragma unroll
       for (int k4 = 0; k4 < 4; ++k4) {
         const f4v av = wrow[k4], dvv = drow[k4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int kb = 4 * k4 + e;
+        for (int ee = 0; ee < 4; ++ee) {
+          const int kb = 4 * k4 + ee;
 #pragma unroll
           for (int nb2 = 0; nb2 < NB; ++nb2)
-            accF[nb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], gB[nb2][kb], accF[nb2], 0, 0, 0);
-          accM = __builtin_amdgcn_mfma_f32_16x16x4f32(dvv[e], phB[kb], accM, 0, 0, 0);
+            accF[nb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ee], gB[nb2][kb], accF[nb2], 0, 0, 0);
+          accM = __builtin_amdgcn_mfma_f32_16x16x4f32(dvv[ee], phB[kb], accM, 0, 0, 0);
         }
       }
-      // accF[nb][r] = dL/df[row 4 ql + r][16 nb + l16]; accM[r] = M[row 4 ql + r][l16]
+      // accF[nb][r] = dL/df[row 4 ql4 + r][16 nb + l16]; accM[r] = M[row 4 ql4 + r][l16]
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 4 * ql + r;
-        if (l16 < 6) sh.mom[w][i][l16] = accM[r];
+        const int i = 4 * ql4 + r;
+        if (l16 < 6) L.mom[i][l16] = accM[r];
         if (i < n && ((cmask >> i) & 1u)) {
-          const int gi = sh.sidx[sh.wl[w][g0 + i]];
+          const int gi = L.ent[i].x;
           float* dst = d_feat + (size_t)(gi - g_off) * C;
 #pragma unroll
           for (int nb2 = 0; nb2 < NB; ++nb2) {
@@ -246,10 +281,9 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
       }
       __builtin_amdgcn_wave_barrier();
       if (lane < n && ((cmask >> lane) & 1u)) {
-        const int j = sh.wl[w][g0 + lane];
-        const int gi = sh.sidx[j];
-        const float4 st = sh.st[j], cn = sh.cn[j];
-        const float* m = sh.mom[w][lane];
+        const int gi = L.ent[lane].x;
+        const float4 st = L.st[lane], cn = L.cn[lane];
+        const float* m = L.mom[lane];
         // pixel offsets d = p - (u, v) with p and (u, v) relative to the quadrant centre
         const float u = st.z - (float)(qx0 + 4), v = st.w - (float)(qy0 + 4);
         const float m1 = m[0], mx = m[1], my = m[2], mxx = m[3], mxy = m[4], myy = m[5];
@@ -266,38 +300,40 @@ __device__ __forceinline__ void bwd_tile(const BatchArgs& a, const ReqDev& q, in
         atomic_add_global(g2 + 4 * gc, -0.5f * sdyy);
         atomic_add_global(g2 + 5 * gc, m1 / cn.w);
       }
-      __builtin_amdgcn_wave_barrier();
     }
+    // ---- the next group has landed: stage it (this group's state is no longer read)
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nn) stage_entry<C>(B, L, lane, en, ox, oy);
+    __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();                            // smax and the buffers are reused by the next tile
 }
 
+// Persistent workgroups of four independent waves over the (tile, quadrant)
+// work items, assigned statically as in the forward blend: wave w of
+// workgroup b takes items 4 b + w, 4 (b + G) + w, ... of the longest-first
+// tile order.
 template <int C>
-__global__ void __launch_bounds__(256) k_render_bwd(BatchArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_render_bwd(BatchArgs a) {
   if (a.dev->overflow) return;
   const BatchHdr h = batch_hdr(a);
-  __shared__ BwdShared<C> sh;
-  __shared__ int s_tile;
-  const int tid = threadIdx.x;
-  for (;;) {
-    if (tid == 0) {                  // queue position -> tile, longest tiles first
-      const int k = atomicAdd(&a.dev->bwd_queue, 1);
-      s_tile = k < h.n_tiles ? a.tile_order[k] : -1;
-    }
-    __syncthreads();
-    const int t = s_tile;
-    __syncthreads();
-    if (t < 0) break;
+  __shared__ __align__(16) float FE[4][GROUP * C];
+  __shared__ double2 RXY[4][GROUP];
+  __shared__ float4 RWQ[4][GROUP];
+  __shared__ float4 RCN[4][GROUP];
+  __shared__ BwdWork<C> LW[4];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const BwdBufs B{FE[wv], RXY[wv], RWQ[wv], RCN[wv]};
+  BwdWork<C>& L = LW[wv];
+  const int n_items = 4 * h.n_tiles;
+  for (int item = 4 * (int)blockIdx.x + wv; item < n_items; item += 4 * (int)gridDim.x) {
+    const int t = a.tile_order[item >> 2];
     const int r = req_of_tile(a, h, t);
     if (r < 0) break;
     const ReqDev& q = batch_req(a, r);
     if (!q.d_img) continue;          // a forward-only request of a mixed batch
     const int lt = t - q.tile_off;
-    bwd_tile<C>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, sh);
-  }
-  if (tid == 0 && atomicAdd(&a.dev->bwd_done, 1) == (int)gridDim.x - 1) {
-    atomicExch(&a.dev->bwd_queue, 0);
-    atomicExch(&a.dev->bwd_done, 0);
+    bwd_quadrant<C>(a, q, t, lt % q.cam.tiles_x, lt / q.cam.tiles_x, item & 3, B, L);
   }
 }
 

@@ -153,7 +153,8 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
   // One list entry (tile-list position pos) against this wave's pixels,
   // given its alpha and feature slice: the stop / blend decisions, then the
   // state updates and the feature accumulation behind a wave-uniform branch.
-  auto visit = [&](const float (&fl)[NM], int pos, float al, bool valid) {
+  int qlast = -1;                     // quadrant-list index of the last entry some pixel blended
+  auto visit = [&](const float (&fl)[NM], int pos, int k, float al, bool valid) {
     const bool ok = valid & (al >= amin);
     const float Tn = __builtin_fmaf(-al, T, T);
     const bool stop = ok & (Tn < 1e-4f);
@@ -162,6 +163,7 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
     if (COUNT && stop) stop_pos = pos;
     const bool blend = ok & !stop;
     if (__builtin_amdgcn_ballot_w64(blend) != 0) {
+      qlast = k;
       if (COUNT) ++wc.steps_blend;
       if (COUNT && blend) ++wc.n_blend;
       const float wgt = blend ? al * T : 0.f;
@@ -223,8 +225,8 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
       const float al1 = blend_alpha(exponent(w1, s1.x, s1.y, fpx, fpy));
       const float al2 = blend_alpha(exponent(w2, s2.x, s2.y, fpx, fpy));
       if (COUNT) wc.steps += has2 ? 2 : 1;
-      visit(fl1, __float_as_int(s1.z), al1, true);
-      visit(fl2, __float_as_int(s2.z), al2, has2);
+      visit(fl1, __float_as_int(s1.z), b0 + j, al1, true);
+      visit(fl2, __float_as_int(s2.z), b0 + j + 1, al2, has2);
     }
     const bool live = __builtin_amdgcn_ballot_w64(amin < 1.f) != 0;
     // ---- batch b+1 has landed; stage its state (batch b's is no longer read)
@@ -277,6 +279,7 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
       }
     }
   }
+  if (lane == 0) a.qcut[4 * gtile + qd] = qlast + 1;   // where the adjoint's backward walk starts
   if (COUNT && inside) {
     // evaluated pairs of the plain walk over the tile's list: every list
     // position up to the stop

@@ -97,6 +97,7 @@ struct Slot {
   int32_t* sorted = nullptr;
   int2* qlist = nullptr;
   int32_t* qcount = nullptr;
+  int32_t* qcut = nullptr;
   float* T_final = nullptr;
   int32_t* last = nullptr;
   float* g2d = nullptr;
@@ -217,6 +218,7 @@ tg::BatchArgs slot_args(const tg_server* s, const Slot& sl) {
   b.sorted = sl.sorted;
   b.qlist = sl.qlist;
   b.qcount = sl.qcount;
+  b.qcut = sl.qcut;
   b.g2d = sl.g2d;
   b.g_cap = s->cap_gauss;
   b.key_cap = s->cap_keys;
@@ -269,7 +271,7 @@ void free_slot(Slot& sl) {
   if (sl.graph_fb) (void)hipGraphDestroy(sl.graph_fb);
   void* d[] = {sl.xy, sl.conic_o, sl.wq, sl.ext, sl.rect, sl.depth, sl.tile_count, sl.tile_start, sl.tile_cursor,
                sl.tile_order,
-               sl.keys, sl.keys_tmp, sl.sorted, sl.qlist, sl.qcount, sl.T_final, sl.last, sl.g2d, sl.dev,
+               sl.keys, sl.keys_tmp, sl.sorted, sl.qlist, sl.qcount, sl.qcut, sl.T_final, sl.last, sl.g2d, sl.dev,
                sl.table_dev,
                sl.hdr_dev};
   for (void* p : d)
@@ -292,7 +294,7 @@ bool alloc_slot(tg_server* s, Slot& sl) {
             dalloc(&sl.tile_count, t) && dalloc(&sl.tile_start, t + 1) && dalloc(&sl.tile_cursor, t) &&
             dalloc(&sl.tile_order, t) &&
             dalloc(&sl.keys, k) && dalloc(&sl.keys_tmp, k) && dalloc(&sl.sorted, k) &&
-            dalloc(&sl.qlist, 4 * k) && dalloc(&sl.qcount, 4 * t) &&
+            dalloc(&sl.qlist, 4 * k) && dalloc(&sl.qcount, 4 * t) && dalloc(&sl.qcut, 4 * t) &&
             dalloc(&sl.T_final, px) && dalloc(&sl.last, px) &&
             dalloc(&sl.g2d, s->opts.backward ? 6 * g : 1) && dalloc(&sl.dev, 1) &&
             dalloc(&sl.table_dev, tg::MAX_BATCH) && dalloc(&sl.hdr_dev, 1) &&

@@ -35,6 +35,7 @@ struct tg_frame {
   int32_t* sorted = nullptr;
   int2* qlist = nullptr;
   int32_t* qcount = nullptr;
+  int32_t* qcut = nullptr;
   float* T_final = nullptr;
   int32_t* last = nullptr;
   float* g2d = nullptr;          // [6][g_cap] backward accumulators
@@ -108,7 +109,7 @@ tg_status dalloc(T** p, size_t count) {
 
 void free_frame(tg_frame* f) {
   void* ptrs[] = {f->xy, f->conic_o, f->wq, f->ext, f->rect, f->depth, f->tile_count, f->tile_start,
-                  f->tile_cursor, f->tile_order, f->keys, f->keys_tmp, f->sorted, f->qlist, f->qcount, f->T_final,
+                  f->tile_cursor, f->tile_order, f->keys, f->keys_tmp, f->sorted, f->qlist, f->qcount, f->qcut, f->T_final,
                   f->last, f->g2d, f->dev, f->table_dev, f->hdr_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -154,6 +155,7 @@ tg::BatchArgs frame_args(tg_frame* f) {
   b.sorted = f->sorted;
   b.qlist = f->qlist;
   b.qcount = f->qcount;
+  b.qcut = f->qcut;
   b.g2d = f->g2d;
   b.g_cap = f->g_cap;
   b.key_cap = f->max_keys;
@@ -272,6 +274,7 @@ tg_status tg_frame_create_views(tg_ctx* ctx, int32_t max_views, int64_t max_n, i
   if (st == TG_OK) st = dalloc(&f->sorted, max_keys);
   if (st == TG_OK) st = dalloc(&f->qlist, 4 * (size_t)max_keys);
   if (st == TG_OK) st = dalloc(&f->qcount, 4 * (size_t)f->max_tiles);
+  if (st == TG_OK) st = dalloc(&f->qcut, 4 * (size_t)f->max_tiles);
   if (st == TG_OK) st = dalloc(&f->T_final, npix);
   if (st == TG_OK) st = dalloc(&f->last, npix);
   if (st == TG_OK) st = dalloc(&f->g2d, (size_t)6 * f->g_cap);

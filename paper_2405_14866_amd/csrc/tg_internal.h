@@ -40,7 +40,11 @@
 //                                  quadrant, in list order: tile t with segment
 //                                  [s, s + n) keeps quadrant q's list at
 //                                  qlist[4 s + q n ...] (room for 4 keys per key),
-//                                  its length at qcount[4 t + q]
+//                                  its length at qcount[4 t + q]; the forward
+//                                  blend writes at qcut[4 t + q] one past the
+//                                  list index of the last entry some pixel of
+//                                  the quadrant blended (0: none), where the
+//                                  adjoint starts its backward walk
 //   per pixel     T_final float32, last int32 (read by the backward pass),
 //                 one slice per request
 //   device state  FrameDev (overflow flag, key count, work queue, counters)
@@ -61,8 +65,6 @@ constexpr int64_t MAX_GAUSS_SPACE = (int64_t)1 << 28;
 
 struct FrameDev {
   int32_t overflow;             // set when the binning needs more keys than the frame holds
-  int32_t bwd_queue;            // next tile of the persistent backward loop
-  int32_t bwd_done;             // backward workgroups finished (the last one resets both)
   int32_t pad;
   int64_t n_keys;               // keys needed by the last binning
   unsigned long long geom_mismatch;  // bit r: request r shares a source whose geometry differs
@@ -147,6 +149,7 @@ struct BatchArgs {
   int32_t* sorted;
   int2* qlist;           // [4 key_cap] quadrant lists
   int32_t* qcount;       // [4 tiles] quadrant list lengths
+  int32_t* qcut;         // [4 tiles] end of the quadrant lists' blended part
   float* g2d;            // [6][g_cap]
   int64_t g_cap;         // capacity of the global Gaussian index space
   int64_t key_cap;
