@@ -270,8 +270,7 @@ __device__ __forceinline__ void bwd_quadrant(const BatchArgs& a, const ReqDev& q
         const int i = 4 * ql4 + r;
         if (l16 < 6) L.mom[i][l16] = accM[r];
         if (i < n && ((cmask >> i) & 1u)) {
-          const int gi = L.ent[i].x;
-          float* dst = d_feat + (size_t)(gi - g_off) * C;
+          float* dst = d_feat + (size_t)(L.ent[i].x - g_off) * C;
 #pragma unroll
           for (int nb2 = 0; nb2 < NB; ++nb2) {
             const int c = 16 * nb2 + l16;
@@ -280,9 +279,14 @@ __device__ __forceinline__ void bwd_quadrant(const BatchArgs& a, const ReqDev& q
         }
       }
       __builtin_amdgcn_wave_barrier();
+      const int gi = L.ent[lane & (GROUP - 1)].x;
+      const float4 st = L.st[lane & (GROUP - 1)], cn = L.cn[lane & (GROUP - 1)];
+      // 2D gradients from the moments: lane j < n forms entry j's six
+      // values; they go out as two instructions of 8 entries x 8 lanes,
+      // each entry's six values one 32-byte row of g2d (six scattered
+      // single-float atomics per entry cost twice as much)
+      float v6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (lane < n && ((cmask >> lane) & 1u)) {
-        const int gi = L.ent[lane].x;
-        const float4 st = L.st[lane], cn = L.cn[lane];
         const float* m = L.mom[lane];
         // pixel offsets d = p - (u, v) with p and (u, v) relative to the quadrant centre
         const float u = st.z - (float)(qx0 + 4), v = st.w - (float)(qy0 + 4);
@@ -291,14 +295,25 @@ __device__ __forceinline__ void bwd_quadrant(const BatchArgs& a, const ReqDev& q
         const float sdxx = mxx - 2.f * u * mx + u * u * m1;
         const float sdxy = mxy - u * my - v * mx + u * v * m1;
         const float sdyy = myy - 2.f * v * my + v * v * m1;
-        float* g2 = a.g2d + (gi + acc_off);
-        const int64_t gc = a.g_cap;
-        atomic_add_global(g2, cn.x * sdx + cn.y * sdy);
-        atomic_add_global(g2 + gc, cn.z * sdy + cn.y * sdx);
-        atomic_add_global(g2 + 2 * gc, -0.5f * sdxx);
-        atomic_add_global(g2 + 3 * gc, -sdxy);
-        atomic_add_global(g2 + 4 * gc, -0.5f * sdyy);
-        atomic_add_global(g2 + 5 * gc, m1 / cn.w);
+        v6[0] = cn.x * sdx + cn.y * sdy;
+        v6[1] = cn.z * sdy + cn.y * sdx;
+        v6[2] = -0.5f * sdxx;
+        v6[3] = -sdxy;
+        v6[4] = -0.5f * sdyy;
+        v6[5] = m1 / cn.w;
+      }
+      const int k = lane & 7;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = 8 * h + (lane >> 3);
+        float vk = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) {
+          const float t = __shfl(v6[kk], e, 64);
+          vk = k == kk ? t : vk;
+        }
+        const int egi = __shfl(gi, e, 64);
+        if (k < 6 && e < n && ((cmask >> e) & 1u)) atomic_add_global(a.g2d + (egi + acc_off) * 8 + k, vk);
       }
     }
     // ---- the next group has landed: stage it (this group's state is no longer read)
@@ -343,8 +358,8 @@ __global__ void k_bwd_zero(BatchArgs a, int c) {
   const BatchHdr h = batch_hdr(a);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int k = 0; k < 6; ++k)
-    for (int64_t i = i0; i < h.g_end; i += stride) a.g2d[k * a.g_cap + i] = 0.f;
+  float4* g2 = reinterpret_cast<float4*>(a.g2d);
+  for (int64_t i = i0; i < 2 * h.g_end; i += stride) g2[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int r = 0; r < h.n_req; ++r) {
     const ReqDev& q = batch_req(a, r);
     if (!q.d_img || !q.d_feat) continue;
@@ -373,7 +388,6 @@ struct RawGrad {
 __device__ __forceinline__ void project_bwd_add(const BatchArgs& a, const ReqDev& qr, int64_t i, int64_t gi,
                                                 RawGrad& g) {
   const int64_t n = qr.n;
-  const int64_t gc = a.g_cap;
   double* dmu = g.dmu;
   double* dls = g.dls;
   double* dq = g.dq;
@@ -415,9 +429,11 @@ __device__ __forceinline__ void project_bwd_add(const BatchArgs& a, const ReqDev
     const double sc = AS[3] * A[3] + AS[4] * A[4] + AS[5] * A[5] + 0.3;
     const double det = sa * sc - sb * sb;
     const double cA = sc / det, cB = -sb / det, cC = sa / det;
-    const double gu = a.g2d[gi], gv = a.g2d[gc + gi];
-    const double gA = a.g2d[2 * gc + gi], gB = a.g2d[3 * gc + gi], gC = a.g2d[4 * gc + gi];
-    const double gO = a.g2d[5 * gc + gi];
+    const float4 g2a = reinterpret_cast<const float4*>(a.g2d)[2 * gi];
+    const float4 g2b = reinterpret_cast<const float4*>(a.g2d)[2 * gi + 1];
+    const double gu = g2a.x, gv = g2a.y;
+    const double gA = g2a.z, gB = g2a.w, gC = g2b.x;
+    const double gO = g2b.y;
     // conic = inverse(Sigma'): G_Sigma = -Q G_Q Q with G_Q = [[gA, gB/2], [gB/2, gC]]
     const double Q[4] = {cA, cB, cB, cC};
     const double GQ[4] = {gA, 0.5 * gB, 0.5 * gB, gC};

@@ -296,7 +296,7 @@ bool alloc_slot(tg_server* s, Slot& sl) {
             dalloc(&sl.keys, k) && dalloc(&sl.keys_tmp, k) && dalloc(&sl.sorted, k) &&
             dalloc(&sl.qlist, 4 * k) && dalloc(&sl.qcount, 4 * t) && dalloc(&sl.qcut, 4 * t) &&
             dalloc(&sl.T_final, px) && dalloc(&sl.last, px) &&
-            dalloc(&sl.g2d, s->opts.backward ? 6 * g : 1) && dalloc(&sl.dev, 1) &&
+            dalloc(&sl.g2d, s->opts.backward ? 8 * g : 1) && dalloc(&sl.dev, 1) &&
             dalloc(&sl.table_dev, tg::MAX_BATCH) && dalloc(&sl.hdr_dev, 1) &&
             halloc(&sl.table_host, tg::MAX_BATCH) && halloc(&sl.hdr_host, 1) && halloc(&sl.dev_host, 1);
   if (!ok) return false;

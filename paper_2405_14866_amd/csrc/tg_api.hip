@@ -277,7 +277,7 @@ tg_status tg_frame_create_views(tg_ctx* ctx, int32_t max_views, int64_t max_n, i
   if (st == TG_OK) st = dalloc(&f->qcut, 4 * (size_t)f->max_tiles);
   if (st == TG_OK) st = dalloc(&f->T_final, npix);
   if (st == TG_OK) st = dalloc(&f->last, npix);
-  if (st == TG_OK) st = dalloc(&f->g2d, (size_t)6 * f->g_cap);
+  if (st == TG_OK) st = dalloc(&f->g2d, (size_t)8 * f->g_cap);
   if (st == TG_OK) st = dalloc(&f->dev, 1);
   if (st == TG_OK && max_views > 1) st = dalloc(&f->table_dev, TG_MAX_VIEWS);
   if (st == TG_OK && max_views > 1) st = dalloc(&f->hdr_dev, 1);

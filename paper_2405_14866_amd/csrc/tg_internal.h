@@ -20,7 +20,9 @@
 //                 rect    uint2    tile rectangle, x0 | x1 << 16, y0 | y1 << 16
 //                                  (empty: x0 > x1)
 //                 depth   uint32   IEEE bits of the float32 view depth
-//                 g2d     float    [6][cap] backward accumulators
+//                 g2d     float    [cap][8] backward accumulators: the six 2D
+//                                  gradients of a Gaussian (u, v, conic A, B, C,
+//                                  opacity) in one 32-byte row
 //   Views of one Gaussian set (extra_views / covered) are requests of their
 //   own (own index range, tiles and pixel state) whose Gaussian loads in
 //   the projection and its adjoint are shared.
@@ -150,7 +152,7 @@ struct BatchArgs {
   int2* qlist;           // [4 key_cap] quadrant lists
   int32_t* qcount;       // [4 tiles] quadrant list lengths
   int32_t* qcut;         // [4 tiles] end of the quadrant lists' blended part
-  float* g2d;            // [6][g_cap]
+  float* g2d;            // [g_cap][8]
   int64_t g_cap;         // capacity of the global Gaussian index space
   int64_t key_cap;
   FrameDev* dev;
