@@ -168,7 +168,10 @@ tg_status tg_frame_work(tg_frame* frame, int64_t* counts, int32_t n_counts);
  * trained through it).  d_feat [c][H][W], d_alpha [H][W] or NULL.  Uses the
  * final transmittance and last-contributor index stored by the last
  * tg_render_fwd of this frame and recomputes every earlier transmittance by
- * walking each pixel's list backwards.  Writes the raw-parameter gradients
+ * walking each pixel's list backwards.  g and bg must be those of that
+ * forward (the stored state describes that render; the library keeps no
+ * copy to compare with, so other values give gradients of no render).
+ * Writes the raw-parameter gradients
  * of `out` (overwritten, device pointers; any of them may be NULL except
  * d_feat, which may be NULL only when g->n == 0). */
 tg_status tg_render_bwd(tg_frame* frame, const tg_gaussians* g, const float* bg,

@@ -43,6 +43,7 @@
 #include <vector>
 
 #include "../../include/tg.h"
+#include "serve_policy.h"
 #include "tg_internal.h"
 
 namespace tg {
@@ -318,24 +319,26 @@ bool alloc_slot(tg_server* s, Slot& sl) {
 // Returns false if nothing could be admitted.
 bool launch_batch(tg_server* s, int slot_id) {
   Slot& sl = s->slots[slot_id];
-  std::vector<uint64_t> batch;
-  int64_t sum_g = 0, sum_k = 0, sum_px = 0;
+  const tg::policy::Limits lim{s->opts.max_batch, s->cap_gauss, s->cap_keys, s->cap_pixels, s->cap_tiles,
+                               s->opts.budget_bytes};
+  std::vector<uint64_t> batch = tg::policy::form_batch(
+      s->queue,
+      [&](uint64_t id) {
+        const Ticket& t = s->tickets[id];
+        return tg::policy::Demand{tg::padded(t.req.g.n), keys_est(s, t.req.g.n),
+                                  (int64_t)t.req.cam.width * t.req.cam.height, tiles_of(t.req.cam), t.footprint,
+                                  t.solo};
+      },
+      lim, s->budget_used);
+  int64_t sum_g = 0, sum_px = 0;
   int32_t sum_t = 0, n_shared = 0;
   bool backward = false;
-  while (!s->queue.empty() && (int)batch.size() < s->opts.max_batch) {
-    Ticket& t = s->tickets[s->queue.front()];
-    const int64_t ng = tg::padded(t.req.g.n), nk = keys_est(s, t.req.g.n);
+  for (size_t b = 0; b < batch.size(); ++b) {
+    Ticket& t = s->tickets[batch[b]];
+    const int64_t ng = tg::padded(t.req.g.n);
     const int64_t npx = (int64_t)t.req.cam.width * t.req.cam.height;
     const int32_t nt = tiles_of(t.req.cam);
-    if (t.solo && !batch.empty()) break;
-    if (sum_g + ng > s->cap_gauss || sum_t + nt > s->cap_tiles || sum_px + npx > s->cap_pixels ||
-        (sum_k + nk > s->cap_keys && !batch.empty()))
-      break;
-    if (s->budget_used + t.footprint > s->opts.budget_bytes) break;
-    s->budget_used += t.footprint;
-    batch.push_back(s->queue.front());
-    s->queue.pop_front();
-    tg::ReqDev& r = sl.table_host[batch.size() - 1];
+    tg::ReqDev& r = sl.table_host[b];
     r = tg::ReqDev{};
     r.mean = t.req.g.mean; r.scale = t.req.g.scale; r.quat = t.req.g.quat;
     r.opacity = t.req.g.opacity; r.feat = t.req.g.feat;
@@ -357,7 +360,7 @@ bool launch_batch(tg_server* s, int slot_id) {
     // reuse of an earlier request's projection and lists: same stream, n and camera
     t.shared = false;
     if (t.req.share && !t.no_share && t.req.g.n > 0) {
-      for (size_t p = 0; p + 1 < batch.size(); ++p) {
+      for (size_t p = 0; p < b; ++p) {
         const Ticket& o = s->tickets[batch[p]];
         const tg::ReqDev& src = sl.table_host[p];
         if (src.src == 0 && o.req.stream_id == t.req.stream_id && o.req.g.n == t.req.g.n &&
@@ -378,8 +381,7 @@ bool launch_batch(tg_server* s, int slot_id) {
     c.W = t.req.cam.width; c.H = t.req.cam.height;
     c.tiles_x = (c.W + tg::TILE - 1) / tg::TILE;
     c.tiles_y = (c.H + tg::TILE - 1) / tg::TILE;
-    sum_g += ng; sum_k += nk; sum_px += npx; sum_t += nt;
-    if (t.solo) break;
+    sum_g += ng; sum_px += npx; sum_t += nt;
   }
   if (batch.empty()) return false;
   *sl.hdr_host = tg::BatchHdr{(int32_t)batch.size(), sum_t, sum_g, n_shared, 0};
@@ -419,21 +421,28 @@ void finish_slot(tg_server* s, Slot& sl) {
     const uint64_t id = sl.tickets[k];
     Ticket& t = s->tickets[id];
     s->budget_used -= t.footprint;
-    if (over && sl.tickets.size() > 1) {
-      t.retries += 1;
-      t.solo = true;
-      retry.push_back(id);
-    } else if (!over && ((mismatch >> k) & 1ull)) {
-      // its geometry differs from the request it shared: render it on its own
-      t.retries += 1;
-      t.no_share = true;
-      retry.push_back(id);
-    } else {
-      t.status = over ? TG_ERR_CAPACITY : TG_OK;
-      t.t_done = t1;
+    switch (tg::policy::retire(over, sl.tickets.size(), ((mismatch >> k) & 1ull) != 0)) {
+      case tg::policy::Outcome::RetrySolo:
+        t.retries += 1;
+        t.solo = true;
+        retry.push_back(id);
+        break;
+      case tg::policy::Outcome::RetryNoShare:   // its geometry differs from the request it shared
+        t.retries += 1;
+        t.no_share = true;
+        retry.push_back(id);
+        break;
+      case tg::policy::Outcome::Capacity:
+        t.status = TG_ERR_CAPACITY;
+        t.t_done = t1;
+        break;
+      case tg::policy::Outcome::Done:
+        t.status = TG_OK;
+        t.t_done = t1;
+        break;
     }
   }
-  for (auto it = retry.rbegin(); it != retry.rend(); ++it) s->queue.push_front(*it);
+  tg::policy::requeue(s->queue, retry);
   sl.tickets.clear();
   sl.busy = false;
   s->done_cv.notify_all();
@@ -466,10 +475,11 @@ void scheduler(tg_server* s) {
     // them until the oldest has waited batch_window_us
     bool hold = false;
     int64_t deadline = 0;
-    if (!s->queue.empty() && s->opts.batch_window_us > 0 && (int)s->queue.size() < s->opts.max_batch) {
+    if (!s->queue.empty()) {
       const Ticket& front = s->tickets[s->queue.front()];
       deadline = front.t_submit + (int64_t)s->opts.batch_window_us * 1000;
-      hold = !front.solo && now_ns() < deadline;
+      hold = tg::policy::holds(s->queue.size(), s->opts.max_batch, s->opts.batch_window_us, front.t_submit,
+                               front.solo, now_ns());
     }
     if (!s->stop && !s->failed && !hold) {
       for (size_t i = 0; i < s->slots.size() && !s->queue.empty(); ++i)

@@ -10,6 +10,8 @@ from __future__ import annotations
 
 import ctypes as ct
 import math
+import threading
+import weakref
 from typing import Optional
 
 import torch
@@ -137,6 +139,12 @@ class Rasterizer:
         self.frame = Frame(self.ctx, max_n, max_w, max_h,
                            max_keys or max(1024, int(max_n * self.kpg * max_views)), max_views)
         self.n_keys = 0
+        # the autograd node of the last differentiable render still awaiting
+        # its backward (a weak reference: dead once that graph is dropped)
+        self.pending = None
+
+    def busy(self) -> bool:
+        return self.pending is not None and self.pending() is not None
 
     def _ensure(self, n, w, h, keys=0, views=1):
         f = self.frame
@@ -277,6 +285,7 @@ class _RasterizeFn(torch.autograd.Function):
                         quats.detach().t().contiguous(), torch.sigmoid(opacity_logits.detach()).contiguous(),
                         feats.detach().contiguous())
         img, alpha = rast.forward(g, cam, bg)
+        rast.pending = weakref.ref(ctx)
         ctx.rast, ctx.g, ctx.bg = rast, g, bg
         ctx.generation = rast.frame.generation
         ctx.frame = rast.frame
@@ -293,6 +302,8 @@ class _RasterizeFn(torch.autograd.Function):
             d_img = torch.zeros((ctx.g.c,) + ctx.hw, device=ctx.g.mean.device)
         gr = rast.backward(ctx.g, d_img.float().contiguous(),
                            None if d_alpha is None else d_alpha.float().contiguous(), ctx.bg)
+        if rast.pending is not None and rast.pending() is ctx:
+            rast.pending = None
         return (gr["mean"].t(), gr["log_scale"].t(), gr["quat"].t(), gr["opacity_logit"],
                 gr["feat"], None, None, None)
 
@@ -304,8 +315,38 @@ def rasterize(means: torch.Tensor, log_scales: torch.Tensor, quats: torch.Tensor
 
     means [N, 3], log_scales [N, 3], quats [N, 4] (w, x, y, z), opacity_logits
     [N], feats [N, C] (C in 8, 16, 32, 64) -> (feat [C, H, W], alpha [H, W])."""
-    if rasterizer is None:
-        dev = means.device.index or 0
-        c = camera_struct(cam)
-        rasterizer = Rasterizer(dev, max_n=max(1, means.shape[0]), max_w=c.width, max_h=c.height)
-    return _RasterizeFn.apply(means, log_scales, quats, opacity_logits, feats, rasterizer, cam, bg)
+    if rasterizer is not None:
+        return _RasterizeFn.apply(means, log_scales, quats, opacity_logits, feats, rasterizer, cam, bg)
+    dev = means.device.index or 0
+    c = camera_struct(cam)
+    rast = _claim(dev, means.shape[0], c.width, c.height)
+    try:
+        return _RasterizeFn.apply(means, log_scales, quats, opacity_logits, feats, rast, cam, bg)
+    finally:
+        if rast.pending is _CLAIMED:
+            rast.pending = None
+
+
+def _CLAIMED():
+    return True
+
+
+_POOL: dict = {}
+_POOL_LOCK = threading.Lock()
+
+
+def _claim(device: int, n: int, w: int, h: int) -> Rasterizer:
+    """A cached rasterizer of the device whose last differentiable render
+    has been differentiated or dropped (a new one when all are in use): its
+    frame is reused and grows as scenes need, so a call allocates nothing in
+    the steady state."""
+    with _POOL_LOCK:
+        pool = _POOL.setdefault(device, [])
+        for r in pool:
+            if not r.busy():
+                r.pending = _CLAIMED
+                return r
+        r = Rasterizer(device, max_n=max(1, n), max_w=w, max_h=h)
+        r.pending = _CLAIMED
+        pool.append(r)
+        return r

@@ -116,6 +116,56 @@ def test_autograd_function_matches_oracle(cfg1):
     print("autograd", compare_backward(got, gpu, oracle.Oracle(sc), dF))
 
 
+def test_rasterize_reuses_cached_rasterizers(cfg1):
+    """rasterize() without a Rasterizer takes one from a per-device pool:
+    the same one again once the previous render was differentiated (no new
+    frame in the steady state), a second one while a render still awaits
+    its backward; both in-flight renders' gradients equal those of renders
+    with rasterizers of their own (to the float atomics' summation order:
+    normwise 1e-5)."""
+    torch = torch_cuda()
+    from paper_2405_14866_amd import rasterize as R
+    dev = "cuda"
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+
+    def params(scale=1.0):
+        return [t(cfg1.mean.T).requires_grad_(), t(np.log(cfg1.scale.astype(np.float64) * scale).T).requires_grad_(),
+                t(cfg1.quat.T).requires_grad_(), t(np.log(cfg1.opacity / (1 - cfg1.opacity))).requires_grad_(),
+                t(cfg1.feat).requires_grad_()]
+
+    dF = t(scenes.make_cfg3_upstream(3, cfg1.c, 64, 64))
+
+    def same(a, b):
+        return float((a - b).norm()) <= 1e-5 * float(b.norm()) + 1e-12
+
+    R._POOL.clear()
+    p0 = params()
+    (R.rasterize(*p0, cfg1.cam)[0] * dF).sum().backward()
+    first = R._POOL[0][0]
+    frame = first.frame
+    p1 = params()
+    (R.rasterize(*p1, cfg1.cam)[0] * dF).sum().backward()
+    assert len(R._POOL[0]) == 1 and R._POOL[0][0].frame is frame          # reused, nothing allocated
+    for a, b in zip(p0, p1):
+        assert same(a.grad, b.grad)
+    # two renders in flight, then both backwards
+    pa, pb = params(), params(1.2)
+    la = (R.rasterize(*pa, cfg1.cam)[0] * dF).sum()
+    lb = (R.rasterize(*pb, cfg1.cam)[0] * dF).sum()
+    assert len(R._POOL[0]) == 2
+    lb.backward()
+    la.backward()
+    for scale, got in ((1.0, pa), (1.2, pb)):
+        ref = params(scale)
+        (R.rasterize(*ref, cfg1.cam, rasterizer=R.Rasterizer(0, max_n=cfg1.n, max_w=64, max_h=64))[0] * dF).sum().backward()
+        for a, b in zip(got, ref):
+            assert same(a.grad, b.grad)
+    # a render under no_grad leaves nothing pending
+    with torch.no_grad():
+        R.rasterize(*[x.detach() for x in params()], cfg1.cam)
+    assert not any(r.busy() for r in R._POOL[0])
+
+
 @pytest.mark.parametrize("which", ["realistic", "scaled_grid"])
 def test_full_size_backward(which):
     """The adjoint at full size in the benchmark's launch configuration: the
