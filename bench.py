@@ -468,6 +468,37 @@ def roof(name, bound, amount, seconds, unit_amount, note):
             "us_per_launch": round(seconds * 1e6, 2), "algorithmic": note}
 
 
+def copy_peak_gbps(torch, reps=10):
+    """HBM bandwidth of a plain 1 GiB device-to-device copy (bytes read +
+    written per second), the reachable stream peak beside the 8 TB/s of the
+    data sheet."""
+    n = 256 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms, _ = timed(torch, lambda: dst.copy_(src), reps)
+    del src, dst
+    return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
+
+
+def cold_frames(torch, step, stream, reps):
+    """The plain path with cold caches: before each timed frame a 512 MiB
+    buffer is rewritten (evicting the L2s and the last-level cache); per
+    kernel and whole-frame medians of HIP-event times."""
+    flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    for e in evs:
+        flush.fill_(1.0)
+        step(e)
+    torch.cuda.synchronize()
+    del flush
+    med = lambda xs: round(pct(xs, 50), 4)
+    return {"frame_ms": med([e[0].elapsed_time(e[3]) for e in evs]),
+            "project_ms": med([e[0].elapsed_time(e[1]) for e in evs]),
+            "bin_sort_ms": med([e[1].elapsed_time(e[2]) for e in evs]),
+            "render_fwd_ms": med([e[2].elapsed_time(e[3]) for e in evs]),
+            "reps": reps, "flush_bytes": 512 << 20}
+
+
 def timed(torch, fn, reps, warmup=3):
     """Average and p99 milliseconds of fn() from events on the current stream."""
     stream = torch.cuda.current_stream()
@@ -800,6 +831,15 @@ def main():
                      "traffic": traffic, "traffic_note": traffic_note,
                      "kernel": "k_render (tg_render_fwd)", "flops_per_launch": flops},
     }
+    # measured stream-copy peak (1 GiB device to device, read + write bytes)
+    # and the plain path cold: a 512 MiB buffer streamed through HBM before
+    # each timed frame evicts the L2s and the 256 MB last-level cache
+    out["hbm"]["copy_peak_GBps"] = copy_peak_gbps(torch)
+    out["hbm"]["frac_of_copy_peak"] = round(hbm_gbps / out["hbm"]["copy_peak_GBps"], 4)
+    out["cold"] = cold_frames(torch, step, stream, min(args.steps, 50))
+    for r in kroof:
+        if r["unit"] == "GB/s":
+            r["frac_of_copy_peak"] = round(r["achieved"] / out["hbm"]["copy_peak_GBps"], 4)
     plain_fps = fps
     # the paper's own figures, context only: its Gaussian count, latent width
     # and feature-map size are not stated, so they are no baseline for this
