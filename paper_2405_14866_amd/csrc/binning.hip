@@ -27,12 +27,13 @@
 //            in flight at once) into LDS and sorted by a stable
 //            least-significant-digit radix sort with 8-bit digits (digit
 //            counts by LDS atomics, ranking within each wave64 by ballot
-//            matching, digit offsets by a wave-level scan) on
-//            the depth bits alone, re-based to the segment's minimum (about
-//            three passes); runs of equal depth (Gaussians at exactly the
-//            same camera depth, rare in practice) are then ordered by index,
-//            one lane per run, and only a run longer than 32 sends the tile
-//            to a sort on the composite (depth - min, index - min) key.
+//            matching, digit offsets by a wave-level scan) on the top 16
+//            bits of the depth re-based to the segment's minimum (two passes
+//            for a typical tile's 20-23 bits); runs of keys equal in those
+//            bits (a few keys: ~750 keys over 65,536 bins) are then ordered
+//            by the whole (depth, index) key, one lane per run, and only a
+//            run longer than 32 sends the tile to a sort on the composite
+//            (depth - min, index - min) key.
 //            Either way the result is the unique (depth, index) order.
 //            Segments up to 2048 keys run in a 32 KB-LDS launch (four
 //            workgroups per CU), larger ones in a second launch with 128 KB
@@ -557,6 +558,7 @@ __device__ __forceinline__ void emit_sorted(const BatchArgs& a, int t, int s, in
 }
 
 constexpr int MAX_TIE_RUN = 32;
+constexpr int SORT_TOP_BITS = 16;   // depth bits the radix passes order; the rest by run insertion
 
 // Segment sort of tile t, whose key count lies in (lo, hi]: sort by depth
 // alone (the key's high half, re-based to its minimum), then order each run
@@ -633,23 +635,29 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int 
       }
     }
     __syncthreads();
-    uint64_t* res = radix_sort<uint64_t*>(bufA, bufB, n, 32, db, sh);
-    // Equal depths are now adjacent, in arbitrary order.  A lane per run of
-    // equal depths orders it by index (insertion sort, runs are short); a
-    // run longer than MAX_TIE_RUN sends the tile to the composite sort.
+    // LSD passes over the top (at most) 16 bits of the re-based depth: two
+    // passes for the 20-23 depth bits of a typical tile instead of three
+    const int low = db > SORT_TOP_BITS ? db - SORT_TOP_BITS : 0;
+    uint64_t* res = radix_sort<uint64_t*>(bufA, bufB, n, 32 + low, db - low, sh);
+    // Keys equal in those bits are now adjacent, in arbitrary order: runs of
+    // them are short (about 750 keys over 65,536 bins per tile).  A lane per
+    // run orders it by the whole (depth, index) key (insertion sort); a run
+    // longer than MAX_TIE_RUN sends the tile to the composite sort.
+    const int hs = 32 + low;
+    auto whole = [](uint64_t x) -> uint64_t { return ((x >> 32) << KEY_MASK_SHIFT) | ((uint32_t)x & KEY_INDEX); };
     int too_long = 0;
     for (int j = tid; j < n; j += 256) {
-      const uint64_t dj = res[j] >> 32;
-      const bool start = (j == 0 || (res[j - 1] >> 32) != dj) && j + 1 < n && (res[j + 1] >> 32) == dj;
+      const uint64_t dj = res[j] >> hs;
+      const bool start = (j == 0 || (res[j - 1] >> hs) != dj) && j + 1 < n && (res[j + 1] >> hs) == dj;
       if (!start) continue;
       int end = j + 1;
-      while (end < n && (res[end] >> 32) == dj && end - j <= MAX_TIE_RUN) ++end;
+      while (end < n && (res[end] >> hs) == dj && end - j <= MAX_TIE_RUN) ++end;
       if (end - j > MAX_TIE_RUN) { too_long = 1; continue; }
-      for (int p = j + 1; p < end; ++p) {        // same depth: compare the index bits
+      for (int p = j + 1; p < end; ++p) {
         const uint64_t v = res[p];
-        const uint32_t vi = (uint32_t)v & KEY_INDEX;
+        const uint64_t vk = whole(v);
         int q = p - 1;
-        while (q >= j && ((uint32_t)res[q] & KEY_INDEX) > vi) { res[q + 1] = res[q]; --q; }
+        while (q >= j && whole(res[q]) > vk) { res[q + 1] = res[q]; --q; }
         res[q + 1] = v;
       }
     }
