@@ -428,16 +428,16 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return m;
 }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t w = __shfl_xor(v, o, 64);
+    const uint32_t w = (uint32_t)__shfl_xor((int)v, o, 64);
     v = w < v ? w : v;
   }
   return v;
 }
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t w = __shfl_xor(v, o, 64);
+    const uint32_t w = (uint32_t)__shfl_xor((int)v, o, 64);
     v = w > v ? w : v;
   }
   return v;
@@ -515,46 +515,61 @@ __device__ __forceinline__ Ptr radix_sort(Ptr a, Ptr b, int n, int shift0, int b
 
 // Output stage of a tile's sort.  get(j, gi, m) yields sorted entry j
 // (Gaussian index gi, quadrant mask m); the entry goes to the tile's index
-// list at s + j and to the list of each quadrant in m as (gi, j).  Rounds
-// of 256 entries: per quadrant a ballot per wave, the four wave counts in
-// LDS, and each entry's slot from the counts of the waves and lanes before
-// it, so every quadrant list keeps the list order.  Quadrant qd's list
-// starts at 4 s + qd n of qlist; its length goes to qcount[4 t + qd].
+// list at s + j and to the list of each quadrant in m as (gi, j).  Wave w
+// owns the contiguous entries [w per, (w + 1) per): it counts its entries'
+// quadrant bits (a ballot per quadrant and 64 entries), the four waves'
+// counts meet in LDS behind one barrier, and each wave then writes its
+// entries from its own offsets, so every quadrant list keeps the list
+// order.  Quadrant qd's list starts at 4 s + qd n of qlist; its length goes
+// to qcount[4 t + qd].
 template <typename Get>
 __device__ __forceinline__ void emit_sorted(const BatchArgs& a, int t, int s, int n, Get get, SortShared& sh) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   int2* out = a.qlist + 4 * (int64_t)s;
   const uint64_t below = lanemask_lt();
-  int base0 = 0, base1 = 0, base2 = 0, base3 = 0;
-  for (int j0 = 0; j0 < n; j0 += 256) {
-    const int j = j0 + tid;
+  const int per = ((n + 255) / 256) * 64;
+  const int b = min(n, w * per), e = min(n, b + per);
+  int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  for (int j0 = b; j0 < e; j0 += 64) {
+    const int j = j0 + lane;
     uint32_t gi = 0, m = 0;
-    if (j < n) {
+    if (j < e) get(j, gi, m);
+    c0 += __popcll(__ballot(m & 1u));
+    c1 += __popcll(__ballot(m & 2u));
+    c2 += __popcll(__ballot(m & 4u));
+    c3 += __popcll(__ballot(m & 8u));
+  }
+  if (lane == 0) {
+    sh.qw[0][w] = c0;
+    sh.qw[1][w] = c1;
+    sh.qw[2][w] = c2;
+    sh.qw[3][w] = c3;
+  }
+  __syncthreads();
+  int base[4];
+#pragma unroll
+  for (int qd = 0; qd < 4; ++qd) {
+    int pre = 0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) pre += ww < w ? sh.qw[qd][ww] : 0;
+    base[qd] = pre;
+  }
+  for (int j0 = b; j0 < e; j0 += 64) {
+    const int j = j0 + lane;
+    uint32_t gi = 0, m = 0;
+    if (j < e) {
       get(j, gi, m);
       a.sorted[s + j] = (int32_t)gi;
     }
-    uint64_t bal[4];
-#pragma unroll
-    for (int qd = 0; qd < 4; ++qd) bal[qd] = __ballot((m >> qd) & 1u);
-    if (lane < 4) sh.qw[lane][w] = __popcll(bal[0]) * (lane == 0) + __popcll(bal[1]) * (lane == 1) +
-                                   __popcll(bal[2]) * (lane == 2) + __popcll(bal[3]) * (lane == 3);
-    __syncthreads();
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd) {
-      int pre = 0, tot = 0;
-#pragma unroll
-      for (int ww = 0; ww < 4; ++ww) {
-        const int v = sh.qw[qd][ww];
-        pre += ww < w ? v : 0;
-        tot += v;
-      }
-      int& base = qd == 0 ? base0 : (qd == 1 ? base1 : (qd == 2 ? base2 : base3));
-      if ((m >> qd) & 1u) out[(int64_t)qd * n + base + pre + __popcll(bal[qd] & below)] = make_int2((int)gi, j);
-      base += tot;
+      const uint64_t bal = __ballot((m >> qd) & 1u);
+      if ((m >> qd) & 1u) out[(int64_t)qd * n + base[qd] + __popcll(bal & below)] = make_int2((int)gi, j);
+      base[qd] += __popcll(bal);
     }
-    __syncthreads();                 // qw is reused by the next round
   }
-  if (tid < 4) a.qcount[4 * t + tid] = tid == 0 ? base0 : (tid == 1 ? base1 : (tid == 2 ? base2 : base3));
+  // (qw is next written after the next tile's first barriers)
+  if (tid < 4) a.qcount[4 * t + tid] = sh.qw[tid][0] + sh.qw[tid][1] + sh.qw[tid][2] + sh.qw[tid][3];
 }
 
 constexpr int MAX_TIE_RUN = 32;
@@ -600,8 +615,10 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int 
       }
     }
   }
-  dmin = wave_min_u64(dmin); dmax = wave_max_u64(dmax);
-  imin = wave_min_u64(imin); imax = wave_max_u64(imax);
+  // depth and index are 32-bit quantities: 32-bit wave reductions (one lane
+  // permute per step instead of two)
+  dmin = wave_min_u32((uint32_t)dmin); dmax = wave_max_u32((uint32_t)dmax);
+  imin = wave_min_u32((uint32_t)imin); imax = wave_max_u32((uint32_t)imax);
   if ((tid & 63) == 0) { sh.red[w][0] = dmin; sh.red[w][1] = dmax; sh.red[w][2] = imin; sh.red[w][3] = imax; }
   __syncthreads();
   for (int q = 0; q < 4; ++q) {
