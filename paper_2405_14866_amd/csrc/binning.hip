@@ -11,8 +11,8 @@
 //            offsets; the key total is checked against the frame capacity
 //            on the device (no host round trip); a counting sort of the
 //            tiles by descending key count (buckets of 32 keys) gives the
-//            order in which the blend's work queue hands tiles out, longest
-//            first, so that the last tiles to start are short ones;
+//            order in which the sort, the blend and its adjoint take tiles,
+//            longest first, so that the last tiles to start are short ones;
 //   k_fill   same LDS binning, then one global atomic per (workgroup, tile)
 //            reserves a contiguous run of the tile's segment and LDS
 //            atomics hand out slots inside it; each slot receives the 64-bit

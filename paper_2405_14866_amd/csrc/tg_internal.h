@@ -32,9 +32,10 @@
 //   there) and its own tiles (its outputs and work items), but reads the 2D
 //   state of the source's range (s_off) and a copy of the source's lists.
 //   per tile      count, start[n_tiles + 1], cursor       int32
-//                 order   int32    tiles by descending key count (the blend's
-//                                  work queue hands out the longest first)
-//   per key       keys    uint64   (depth << 32) | global index, grouped by tile
+//                 order   int32    tiles by descending key count (the sort,
+//                                  blend and adjoint take the longest first)
+//   per key       keys    uint64   (depth << 32) | (quadrant mask << 28) |
+//                                  global index, grouped by tile
 //                 keys_tmp uint64  scratch for segments too long for LDS
 //                 sorted  int32    global index, per tile in (depth, index) order
 //                 qlist   int2     (global index, position in the tile's list) of the
@@ -49,7 +50,7 @@
 //                                  adjoint starts its backward walk
 //   per pixel     T_final float32, last int32 (read by the backward pass),
 //                 one slice per request
-//   device state  FrameDev (overflow flag, key count, work queue, counters)
+//   device state  FrameDev (overflow flag, key count, work counters)
 #pragma once
 
 #include <hip/hip_runtime.h>
