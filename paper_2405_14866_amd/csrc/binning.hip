@@ -23,22 +23,24 @@
 //            registers; indices stay below 2^28).  The order inside a
 //            segment is not deterministic here; the sort makes it so;
 //   k_sort   one 256-lane workgroup per tile, tiles taken longest first
-//            (the scan's order): the segment is loaded (eight keys per lane
-//            in flight at once) into LDS and sorted by a stable
-//            least-significant-digit radix sort with 8-bit digits (digit
-//            counts by LDS atomics, ranking within each wave64 by ballot
-//            matching, digit offsets by a wave-level scan) on the top 16
-//            bits of the depth re-based to the segment's minimum (two passes
-//            for a typical tile's 20-23 bits); runs of keys equal in those
-//            bits (a few keys: ~750 keys over 65,536 bins) are then ordered
-//            by the whole (depth, index) key, one lane per run, and only a
-//            run longer than 32 sends the tile to a sort on the composite
-//            (depth - min, index - min) key.
+//            (the scan's order): the segment is loaded eight keys per lane
+//            (all loads in flight at once) and stays in those registers
+//            while it is ordered on the top 16 bits of the depth re-based
+//            to the segment's minimum: a 10-bit pass that needs no
+//            stability (LDS atomics hand out slots) straight from the
+//            registers into one LDS buffer, then a stable 6-bit pass
+//            (each wave ranks its contiguous range by ballot matching and
+//            a running count per digit, then scatters in place); runs of
+//            keys equal in those bits (a few keys: ~750 keys over 65,536
+//            bins) are then ordered by the whole (depth, index) key, one
+//            lane per run, and only a run longer than 32 sends the tile to
+//            a sort on the composite (depth - min, index - min) key.
 //            Either way the result is the unique (depth, index) order.
-//            Segments up to 2048 keys run in a 32 KB-LDS launch (four
-//            workgroups per CU), larger ones in a second launch with 128 KB
-//            whose small grid walks the head of the tile order, and beyond
-//            8192 keys on global scratch buffers.  The sorted segment is
+//            Segments up to 2048 keys run in a launch with one workgroup
+//            per tile and 22 KB of LDS (six workgroups per CU), larger ones
+//            in a second launch with 64 KB whose small grid walks the head
+//            of the tile order, and beyond 8192 keys (or with a too long
+//            run) on global scratch buffers.  The sorted segment is
 //            written as the tile's index list and, from the same registers,
 //            split into four quadrant lists: entry j goes to the list of
 //            each quadrant its key's mask holds, in list order, as
@@ -455,11 +457,108 @@ __device__ __forceinline__ int bit_length(uint64_t x) { return x ? 64 - __clzll(
 
 // Shared scratch of the segment sort.
 struct SortShared {
-  uint32_t hist[4][256];   // per-wave digit counts, then running offsets
+  union {
+    uint32_t bins[1024];     // digit counts of an unstable pass, then offsets
+    uint32_t hist[4][256];   // per-wave digit counts of a global-memory pass
+  };
+  uint32_t whist[4][64];     // per-wave digit counts of a stable 6-bit pass
   uint32_t wtot[4];
   uint64_t red[4][4];
-  int32_t qw[4][4];        // per-wave quadrant counts of the output stage
+  int32_t qw[4][4];          // per-wave quadrant counts of the output stage
 };
+
+constexpr int U_BITS = 10;   // digit of an unstable pass (1024 counters)
+constexpr int S_BITS = 6;    // digit of a stable pass (64 counters per wave)
+
+// Pass over the digit (x >> shift) & mask (at most U_BITS bits) that keeps
+// no order among equal digits: an LDS atomic hands each element a slot in
+// its digit's run.  The elements are this lane's x[i] for the bits i set
+// in live; they land in buf[0, n) (which no lane reads during the pass, so
+// buf may hold them on entry).  bins is zero on entry and on exit.
+template <int K>
+__device__ __forceinline__ void pass_unstable(const uint64_t (&x)[K], uint32_t live, uint64_t* buf, int shift,
+                                              uint32_t mask, SortShared& sh) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  uint32_t slot[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+    slot[i] = ((live >> i) & 1u) ? atomicAdd(&sh.bins[(uint32_t)(x[i] >> shift) & mask], 1u) : 0u;
+  __syncthreads();
+  // exclusive offsets: lane tid owns the counters [4 tid, 4 tid + 4)
+  const uint4 c = reinterpret_cast<const uint4*>(sh.bins)[tid];
+  const uint32_t tot = c.x + c.y + c.z + c.w;
+  const uint32_t incl = wave_incl_scan(tot, lane);
+  if (lane == 63) sh.wtot[w] = incl;
+  __syncthreads();
+  uint32_t base = incl - tot;
+  for (int q = 0; q < w; ++q) base += sh.wtot[q];
+  reinterpret_cast<uint4*>(sh.bins)[tid] = make_uint4(base, base + c.x, base + c.x + c.y, base + c.x + c.y + c.z);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+    if ((live >> i) & 1u) buf[sh.bins[(uint32_t)(x[i] >> shift) & mask] + slot[i]] = x[i];
+  __syncthreads();
+  reinterpret_cast<uint4*>(sh.bins)[tid] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Stable pass over the digit (x >> shift) & 63 of buf[0, n), in place.
+// Wave w takes the contiguous range [w per, (w + 1) per) into registers,
+// 64 elements at a time in order, and ranks each element among the
+// wave's equal digits before it: ballot matching inside the 64 gives the
+// rank among them and their count, and the lowest lane of each digit adds
+// that count to the wave's running count of the digit (an LDS atomic whose
+// old value its group reads back).  One wave turns the per-wave counts
+// into offsets (digit-major, wave-minor); every element then goes to its
+// offset plus its rank.  whist is zero on entry and on exit.
+template <int K>
+__device__ __forceinline__ void pass_stable(uint64_t* buf, int n, int shift, SortShared& sh) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int per = ((n + 255) / 256) * 64;
+  const int b = min(n, w * per), e = min(n, b + per);
+  const uint64_t below = lanemask_lt();
+  uint64_t x[K];
+  uint32_t rank[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int j = b + 64 * i + lane;
+    x[i] = j < e ? buf[j] : 0ull;
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    rank[i] = 0;
+    if (b + 64 * i >= e) continue;
+    const bool valid = b + 64 * i + lane < e;
+    const uint32_t d = (uint32_t)(x[i] >> shift) & 63u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int k = 0; k < S_BITS; ++k) {
+      const bool bit = (d >> k) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const int lead = __ffsll((unsigned long long)peers) - 1;
+    uint32_t old = 0;
+    if (valid && lane == lead) old = atomicAdd(&sh.whist[w][d], (uint32_t)__popcll(peers));
+    old = (uint32_t)__shfl((int)old, lead & 63, 64);
+    rank[i] = old + (uint32_t)__popcll(peers & below);
+  }
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t h0 = sh.whist[0][lane], h1 = sh.whist[1][lane], h2 = sh.whist[2][lane], h3 = sh.whist[3][lane];
+    const uint32_t tot = h0 + h1 + h2 + h3;
+    const uint32_t base = wave_incl_scan(tot, lane) - tot;
+    sh.whist[0][lane] = base;
+    sh.whist[1][lane] = base + h0;
+    sh.whist[2][lane] = base + h0 + h1;
+    sh.whist[3][lane] = base + h0 + h1 + h2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+    if (b + 64 * i + lane < e) buf[sh.whist[w][(uint32_t)(x[i] >> shift) & 63u] + rank[i]] = x[i];
+  __syncthreads();
+  sh.whist[w][lane] = 0;   // the wave's own row; the next pass counts into it after a barrier
+}
 
 // One stable pass over digit (key >> shift) & 255 of elements [0, n).
 // Wave w owns the contiguous element range [w * per, (w + 1) * per) and
@@ -573,47 +672,57 @@ __device__ __forceinline__ void emit_sorted(const BatchArgs& a, int t, int s, in
 }
 
 constexpr int MAX_TIE_RUN = 32;
-constexpr int SORT_TOP_BITS = 16;   // depth bits the radix passes order; the rest by run insertion
+constexpr int SORT_TOP_BITS = U_BITS + S_BITS;   // depth bits the passes order; the rest by run insertion
 
 // Segment sort of tile t, whose key count lies in (lo, hi]: sort by depth
 // alone (the key's high half, re-based to its minimum), then order each run
 // of equal depths by index; only a run longer than MAX_TIE_RUN makes the
 // tile redo the sort on the composite (depth, index) key.  Either way the
-// result is the (depth, index) order.  Segments above CAP run the
-// composite sort on the global scratch buffers.  The quadrant mask rides
-// along: in the low half of the depth-only element (above the index, which
-// alone is compared among equal depths), below the composite key (whose
-// (depth, index) part is unique, so the mask never decides the order).
+// result is the (depth, index) order.  Segments up to CAP keys stay in the
+// registers they are loaded into (CAP / 256 per lane) and in one LDS
+// buffer: an unstable pass on the lower digit straight from the registers,
+// then a stable pass on the top six bits.  Larger segments, and the rare
+// ones with a too long run, run the composite sort with 8-bit stable passes
+// on the global scratch buffers.
+// The quadrant mask rides along: in the low half of the depth-only element
+// (above the index, which alone is compared among equal depths), below the
+// composite key (whose (depth, index) part is unique, so the mask never
+// decides the order).
 template <int CAP>
-__device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int n, uint64_t* bufA, uint64_t* bufB,
-                                          SortShared& sh) {
+__device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int n, uint64_t* buf, SortShared& sh) {
+  constexpr int K = CAP / 256;
+  static_assert(K >= 1 && K <= 32, "one live bit per register slot");
   const int tid = threadIdx.x, w = tid >> 6;
   if (n == 1) {
     const uint32_t lo = (uint32_t)a.keys[s];
     emit_sorted(a, t, s, 1, [&](int, uint32_t& gi, uint32_t& m) { gi = lo & KEY_INDEX; m = lo >> KEY_MASK_SHIFT; }, sh);
     return;
   }
-  for (int q = tid; q < 4 * 256; q += 256) (&sh.hist[0][0])[q] = 0;
-  // ranges of depth and index in the segment; the keys are loaded eight per
-  // lane with all loads in flight at once (a segment up to 2048 keys stays
-  // in registers until it is re-based into LDS)
-  constexpr int PER = 8;
-  uint64_t kv[PER];
+  // ranges of depth and index in the segment; a segment up to CAP keys is
+  // loaded K keys per lane with all loads in flight at once and stays in
+  // registers
+  uint64_t kv[K];
+  uint32_t live = 0;
   uint64_t dmin = ~0ull, dmax = 0, imin = ~0ull, imax = 0;
-  for (int j0 = 0; j0 < n; j0 += 256 * PER) {
+  auto widen = [&](uint64_t k) {
+    const uint64_t d = k >> 32, ix = (uint32_t)k & KEY_INDEX;
+    dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
+    imin = ix < imin ? ix : imin; imax = ix > imax ? ix : imax;
+  };
+  if (n <= CAP) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int j = j0 + tid + 256 * i;
+    for (int i = 0; i < K; ++i) {
+      const int j = tid + 256 * i;
       kv[i] = j < n ? a.keys[s + j] : 0ull;
     }
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      if (j0 + tid + 256 * i < n) {
-        const uint64_t d = kv[i] >> 32, ix = (uint32_t)kv[i] & KEY_INDEX;
-        dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
-        imin = ix < imin ? ix : imin; imax = ix > imax ? ix : imax;
+    for (int i = 0; i < K; ++i)
+      if (tid + 256 * i < n) {
+        live |= 1u << i;
+        widen(kv[i]);
       }
-    }
+  } else {
+    for (int j = tid; j < n; j += 256) widen(a.keys[s + j]);
   }
   // depth and index are 32-bit quantities: 32-bit wave reductions (one lane
   // permute per step instead of two)
@@ -638,24 +747,25 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int 
     m = (uint32_t)e & 15u;
   };
   if (n <= CAP) {
-    // depth-only pass set: element = (depth - dmin) << 32 | (mask, index)
-    if (n <= 256 * PER) {
+    // depth-only element: (depth - dmin) << 32 | (mask, index)
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int j = tid + 256 * i;
-        if (j < n) bufA[j] = (((kv[i] >> 32) - dmin) << 32) | (kv[i] & 0xffffffffull);
-      }
-    } else {
-      for (int j = tid; j < n; j += 256) {
-        const uint64_t k = a.keys[s + j];
-        bufA[j] = (((k >> 32) - dmin) << 32) | (k & 0xffffffffull);
-      }
-    }
-    __syncthreads();
-    // LSD passes over the top (at most) 16 bits of the re-based depth: two
-    // passes for the 20-23 depth bits of a typical tile instead of three
+    for (int i = 0; i < K; ++i) kv[i] = (((kv[i] >> 32) - dmin) << 32) | (kv[i] & 0xffffffffull);
+    // the top (at most) 16 bits of the re-based depth: one unstable pass on
+    // their lower part, one stable pass on their top six bits (a typical
+    // tile's depths span 20-23 bits)
     const int low = db > SORT_TOP_BITS ? db - SORT_TOP_BITS : 0;
-    uint64_t* res = radix_sort<uint64_t*>(bufA, bufB, n, 32 + low, db - low, sh);
+    const int nb = db - low;
+    if (nb == 0) {
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if ((live >> i) & 1u) buf[tid + 256 * i] = kv[i];
+      __syncthreads();
+    } else if (nb <= U_BITS) {
+      pass_unstable<K>(kv, live, buf, 32 + low, (1u << nb) - 1u, sh);
+    } else {
+      pass_unstable<K>(kv, live, buf, 32 + low, (1u << (nb - S_BITS)) - 1u, sh);
+      pass_stable<K>(buf, n, 32 + low + nb - S_BITS, sh);
+    }
     // Keys equal in those bits are now adjacent, in arbitrary order: runs of
     // them are short (about 750 keys over 65,536 bins per tile).  A lane per
     // run orders it by the whole (depth, index) key (insertion sort); a run
@@ -664,70 +774,84 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int 
     auto whole = [](uint64_t x) -> uint64_t { return ((x >> 32) << KEY_MASK_SHIFT) | ((uint32_t)x & KEY_INDEX); };
     int too_long = 0;
     for (int j = tid; j < n; j += 256) {
-      const uint64_t dj = res[j] >> hs;
-      const bool start = (j == 0 || (res[j - 1] >> hs) != dj) && j + 1 < n && (res[j + 1] >> hs) == dj;
+      const uint64_t dj = buf[j] >> hs;
+      const bool start = (j == 0 || (buf[j - 1] >> hs) != dj) && j + 1 < n && (buf[j + 1] >> hs) == dj;
       if (!start) continue;
       int end = j + 1;
-      while (end < n && (res[end] >> hs) == dj && end - j <= MAX_TIE_RUN) ++end;
+      while (end < n && (buf[end] >> hs) == dj && end - j <= MAX_TIE_RUN) ++end;
       if (end - j > MAX_TIE_RUN) { too_long = 1; continue; }
       for (int p = j + 1; p < end; ++p) {
-        const uint64_t v = res[p];
+        const uint64_t v = buf[p];
         const uint64_t vk = whole(v);
         int q = p - 1;
-        while (q >= j && whole(res[q]) > vk) { res[q + 1] = res[q]; --q; }
-        res[q + 1] = v;
+        while (q >= j && whole(buf[q]) > vk) { buf[q + 1] = buf[q]; --q; }
+        buf[q + 1] = v;
       }
     }
-    if (__syncthreads_or(too_long)) {
-      for (int j = tid; j < n; j += 256) bufA[j] = composite(a.keys[s + j]);
-      __syncthreads();
-      res = radix_sort<uint64_t*>(bufA, bufB, n, 0, cbits, sh);
-      emit_sorted(a, t, s, n, [&](int j, uint32_t& gi, uint32_t& m) { from_composite(res[j], gi, m); }, sh);
-    } else {
+    if (!__syncthreads_or(too_long)) {
       emit_sorted(a, t, s, n, [&](int j, uint32_t& gi, uint32_t& m) {
-        const uint32_t lo = (uint32_t)res[j];
+        const uint32_t lo = (uint32_t)buf[j];
         gi = lo & KEY_INDEX;
         m = lo >> KEY_MASK_SHIFT;
       }, sh);
+      return;
     }
-  } else {
-    uint64_t* g0 = a.keys + s;
-    uint64_t* g1 = a.keys_tmp + s;
-    for (int j = tid; j < n; j += 256) g0[j] = composite(g0[j]);
-    __syncthreads();
-    const uint64_t* res = radix_sort<uint64_t*>(g0, g1, n, 0, cbits, sh);
-    emit_sorted(a, t, s, n, [&](int j, uint32_t& gi, uint32_t& m) { from_composite(res[j], gi, m); }, sh);
   }
+  // the composite sort on the global scratch buffers: segments above CAP,
+  // and segments with a run of equal depths too long for insertion (the
+  // keys in global memory are still the unsorted ones)
+  uint64_t* g0 = a.keys + s;
+  uint64_t* g1 = a.keys_tmp + s;
+  for (int j = tid; j < n; j += 256) g0[j] = composite(g0[j]);
+  __syncthreads();
+  const uint64_t* res = radix_sort<uint64_t*>(g0, g1, n, 0, cbits, sh);
+  emit_sorted(a, t, s, n, [&](int j, uint32_t& gi, uint32_t& m) { from_composite(res[j], gi, m); }, sh);
 }
 
 // Tiles are taken in the scan's order (descending key count), so the
-// longest segments start first.  With LOOP, a small grid walks the head
-// of that order and stops at the first tile too short for it.
+// longest segments start first.  Without LOOP the grid covers every tile
+// slot of the batch and workgroup i takes the i-th tile of that order (no
+// loop, so nothing is kept live from one tile to the next); with LOOP, a
+// small grid walks the head of that order and stops at the first tile too
+// short for it.
 template <int CAP, bool LOOP>
-__global__ void __launch_bounds__(256) k_sort(BatchArgs a, int lo, int hi) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 2048 ? 6 : 1, 8)))
+k_sort(BatchArgs a, int lo, int hi) {
   if (a.dev->overflow) return;
-  __shared__ uint64_t bufA[CAP];
-  __shared__ uint64_t bufB[CAP];
+  __shared__ uint64_t buf[CAP];
   __shared__ SortShared sh;
   const BatchHdr h = batch_hdr(a);
   const int nt = h.n_tiles;
+  if (!LOOP && (int)blockIdx.x >= nt) return;
+  // the passes keep their counters zero between uses
+  reinterpret_cast<uint4*>(sh.bins)[threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
+  (&sh.whist[0][0])[threadIdx.x] = 0u;
+  __syncthreads();
+  auto job = [&](int i, int& t, int& s, int& n) {   // 1: sort tile t, 0: skip it, -1: stop
+    t = a.tile_order[i];
+    s = a.tile_start[t];
+    n = a.tile_start[t + 1] - s;
+    if (n <= lo) return LOOP && n < ((ORDER_BUCKETS - 1) << ORDER_SHIFT) ? -1 : 0;   // the rest are shorter still
+    if (n > hi) return 0;
+    if (h.n_shared > 0 && batch_req(a, req_of_tile(a, h, t)).src != 0) return 0;   // copied later
+    return 1;
+  };
+  int t, s, n;
+  if (!LOOP) {
+    if (job(blockIdx.x, t, s, n) == 1) sort_tile<CAP>(a, t, s, n, buf, sh);
+    return;
+  }
   for (int i = blockIdx.x; i < nt; i += gridDim.x) {
-    const int t = a.tile_order[i];
-    const int s = a.tile_start[t];
-    const int n = a.tile_start[t + 1] - s;
-    if (n <= lo) {
-      if (LOOP && n < ((ORDER_BUCKETS - 1) << ORDER_SHIFT)) break;   // the rest are shorter still
-      continue;
-    }
-    if (n > hi) continue;
-    if (h.n_shared > 0 && batch_req(a, req_of_tile(a, h, t)).src != 0) continue;   // copied later
-    sort_tile<CAP>(a, t, s, n, bufA, bufB, sh);
+    const int r = job(i, t, s, n);
+    if (r < 0) break;
+    if (r == 0) continue;
+    sort_tile<CAP>(a, t, s, n, buf, sh);
     __syncthreads();                 // LDS is reused by the next tile
   }
 }
 
-constexpr int SORT_SMALL = 2048;   // segments up to this size: 32 KB of LDS keys, 4 workgroups per CU
-constexpr int SORT_LARGE = 8192;   // larger segments: 128 KB of LDS keys, beyond it global scratch
+constexpr int SORT_SMALL = 2048;   // segments up to this size: 16 KB of LDS keys, 7 workgroups per CU
+constexpr int SORT_LARGE = 8192;   // larger segments: 64 KB of LDS keys, beyond it global scratch
 
 }  // namespace
 
@@ -750,6 +874,7 @@ hipError_t launch_bin_sort(const BatchArgs& a, int64_t grid_gauss, int32_t grid_
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(k_fill, dim3(grid), dim3(1024), shm, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
+  // gt is the batch's tile capacity: one workgroup per tile slot
   hipLaunchKernelGGL((k_sort<SORT_SMALL, false>), dim3(gt), dim3(256), 0, s, a, 0, SORT_SMALL);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL((k_sort<SORT_LARGE, true>), dim3(gt < 256 ? gt : 256), dim3(256), 0, s, a, SORT_SMALL,
