@@ -146,7 +146,7 @@ def test_run_twice_is_bitwise_identical(cfg1):
 
 
 def test_long_tile_segment_uses_global_sort():
-    """More keys in one tile than the 128 KB LDS sort holds (8192): 12,000
+    """More keys in one tile than the 64 KB LDS sort holds (8192): 12,000
     tiny Gaussians inside tile (0, 0) (radius 2 px around centres in
     [2, 14] px), so that segment is sorted on the global scratch buffers with
     the composite (depth, index) passes; lists stay bit-exact."""
@@ -170,9 +170,10 @@ def test_equal_depth_runs_take_the_composite_sort(n_tie, n_other):
     """A run of more than 32 keys with bit-identical float32 depth in one tile
     (Gaussians on the fronto-parallel plane z = 1.5 under the identity camera,
     so t_z = z exactly) sends the tile to the sort on the composite
-    (depth, index) key; with 400 keys that is the 32 KB-LDS launch, with 3,050
-    the 128 KB one.  The run is interleaved in index order with Gaussians at
-    other depths; lists stay bit-exact (ties in index order)."""
+    (depth, index) key (on the global scratch buffers, from the 22 KB-LDS
+    launch with 400 keys and from the 64 KB one with 3,050).  The run is
+    interleaved in index order with Gaussians at other depths; lists stay
+    bit-exact (ties in index order)."""
     rng = np.random.default_rng(100 + n_tie)
     n = n_tie + n_other
     z = rng.uniform(1.0, 2.0, n)
@@ -185,6 +186,43 @@ def test_equal_depth_runs_take_the_composite_sort(n_tie, n_other):
     ora = oracle.Oracle(sc)
     _, key, _ = ora.spec()
     assert (key == np.float32(1.5).view(np.uint32)).sum() == n_tie
+    gpu, _, _ = gpu_render(sc)
+    assert np.diff(gpu["tile_start"])[0] == n
+    compare_lists(gpu, ora)
+    compare_forward(gpu, ora)
+
+
+@pytest.mark.parametrize("case", ["one_depth_20", "ten_bit_span_300", "keys_2048", "keys_2049"])
+def test_segment_sort_branches(case):
+    """The segment sort's other branches, each with every key in tile (0, 0)
+    (Gaussians of radius 2 px around centres in [3, 13] px, identity camera,
+    so the float32 depth key is the bits of z): 20 keys at one depth (no
+    radix pass, one run ordered by index); 300 keys whose depths lie within
+    900 float32 steps (a span of at most 10 bits: the unstable pass alone,
+    with ties); exactly 2048 keys (the largest segment of the 22 KB-LDS
+    launch) and 2049 (the smallest of the 64 KB one).  Lists stay bit-exact."""
+    rng = np.random.default_rng({"one_depth_20": 1, "ten_bit_span_300": 2, "keys_2048": 3, "keys_2049": 4}[case])
+    if case == "one_depth_20":
+        n = 20
+        z = np.full(n, 1.5)
+    elif case == "ten_bit_span_300":
+        n = 300
+        bits = np.float32(1.5).view(np.uint32) + rng.integers(0, 900, n).astype(np.uint32)
+        z = bits.view(np.float32).astype(np.float64)
+    else:
+        n = 2048 if case == "keys_2048" else 2049
+        z = rng.uniform(1.0, 3.0, n)
+    u = rng.uniform(3, 13, n); v = rng.uniform(3, 13, n)
+    means = np.stack([(u - 32) * z / 64, (v - 32) * z / 64, z])
+    sc = scenes.single_gaussian_scene(means, 0.002, opacity=rng.uniform(0.05, 0.5, n),
+                                      feat=rng.standard_normal((n, 8)), cam=_cam())
+    ora = oracle.Oracle(sc)
+    _, key, _ = ora.spec()
+    span = int(key.max()) - int(key.min())
+    if case == "one_depth_20":
+        assert span == 0
+    if case == "ten_bit_span_300":
+        assert 0 < span < 1024 and len(np.unique(key)) < n
     gpu, _, _ = gpu_render(sc)
     assert np.diff(gpu["tile_start"])[0] == n
     compare_lists(gpu, ora)
