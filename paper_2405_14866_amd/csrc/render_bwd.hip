@@ -324,10 +324,11 @@ __device__ __forceinline__ void bwd_quadrant(const BatchArgs& a, const ReqDev& q
   }
 }
 
-// Persistent workgroups of four independent waves over the (tile, quadrant)
-// work items, assigned statically as in the forward blend: wave w of
-// workgroup b takes items 4 b + w, 4 (b + G) + w, ... of the longest-first
-// tile order.
+// Workgroups of four independent waves, one per tile slot, over the
+// (tile, quadrant) work items as in the forward blend: wave w of workgroup
+// b takes item 4 b + w of the longest-first tile order (and 4 (b + G) + w,
+// ... for a smaller grid of G workgroups), so that the hardware's in-order
+// start of workgroups schedules the tiles greedily, longest first.
 template <int C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_render_bwd(BatchArgs a) {
   if (a.dev->overflow) return;
@@ -367,11 +368,9 @@ __global__ void k_bwd_zero(BatchArgs a, int c) {
   }
 }
 
-constexpr int BWD_PERSISTENT_WG = 256 * 6;
-
 template <int C>
 hipError_t launch_bwd_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s) {
-  const int grid = grid_tiles < BWD_PERSISTENT_WG ? (grid_tiles > 0 ? grid_tiles : 1) : BWD_PERSISTENT_WG;
+  const int grid = grid_tiles > 0 ? grid_tiles : 1;   // one workgroup per tile slot
   hipLaunchKernelGGL((k_render_bwd<C>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -56,7 +56,6 @@
 namespace tg {
 namespace {
 
-constexpr int PERSISTENT_WG = 256 * 8;   // persistent workgroups (>= resident capacity)
 
 
 // this lane's C/4 contiguous features of a row (LDS), for the MFMA B
@@ -287,19 +286,22 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
   }
 }
 
-// Persistent workgroups of four independent waves.  Work item i is quadrant
-// i & 3 of the tile at position i >> 2 of the tile order (longest tiles
-// first); wave w of workgroup b takes items 4 b + w, 4 (b + G) + w, ... for
-// a grid of G workgroups, so the four waves of a workgroup blend the four
-// quadrants of one tile (sharing its Gaussians in the CU's cache) and each
-// blends alone, without a workgroup barrier.  The assignment is static: one
-// device-wide atomic counter handing out items to every wave serialises at
-// that counter (measured: it doubled the blend's time), while the longest-
-// first order plus the hardware's dispatch of the workgroups beyond the
-// resident ones keeps the load even.  TABLE: the batch's requests come from
-// the device table (a replayed serving batch) rather than inline (a single
-// render); the two are separate instantiations so that each keeps its own
-// launch statistics.
+// Workgroups of four independent waves, one per tile slot of the batch.
+// Work item i is quadrant i & 3 of the tile at position i >> 2 of the tile
+// order (longest tiles first); wave w of workgroup b takes item 4 b + w
+// (and 4 (b + G) + w, ... if a grid of G workgroups were smaller than the
+// tile count), so the four waves of a workgroup blend the four quadrants of
+// one tile (sharing its Gaussians in the CU's cache) and each blends alone,
+// without a workgroup barrier.  The hardware starts workgroups in index
+// order as compute units free up, which makes the schedule a greedy
+// longest-first one: measured against 2,048 persistent workgroups that
+// each walked two fixed positions of the order, 6.5 % less time on the
+// realistic frame.  A device-wide atomic counter handing out items
+// serialises at that counter instead (measured: it doubled the blend's
+// time).  TABLE: the batch's requests come from the device table (a
+// replayed serving batch) rather than inline (a single render); the two
+// are separate instantiations so that each keeps its own launch
+// statistics.
 template <int C, bool COUNT, bool TABLE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_render(BatchArgs a) {
   if (a.dev->overflow) return;
@@ -350,7 +352,7 @@ __global__ void k_zero_work(FrameDev* d) {
 
 template <int C>
 hipError_t launch_c(const BatchArgs& a, int32_t grid_tiles, hipStream_t s, bool count) {
-  const int grid = grid_tiles < PERSISTENT_WG ? (grid_tiles > 0 ? grid_tiles : 1) : PERSISTENT_WG;
+  const int grid = grid_tiles > 0 ? grid_tiles : 1;   // one workgroup per tile slot
   if (count) {                        // work counts: single renders only
     if (a.table) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(1), 0, s, a.dev);
