@@ -817,12 +817,14 @@ __device__ __forceinline__ void sort_tile(const BatchArgs& a, int t, int s, int 
 template <int CAP, bool LOOP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 2048 ? 6 : 1, 8)))
 k_sort(BatchArgs a, int lo, int hi) {
-  if (a.dev->overflow) return;
   __shared__ uint64_t buf[CAP];
   __shared__ SortShared sh;
+  // both reads in flight before the first branch: most workgroups of a
+  // serving slot's launch lie past the batch's tiles and leave here
+  const int overflow = a.dev->overflow;
   const BatchHdr h = batch_hdr(a);
   const int nt = h.n_tiles;
-  if (!LOOP && (int)blockIdx.x >= nt) return;
+  if (overflow != 0 || (!LOOP && (int)blockIdx.x >= nt)) return;
   // the passes keep their counters zero between uses
   reinterpret_cast<uint4*>(sh.bins)[threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
   (&sh.whist[0][0])[threadIdx.x] = 0u;

@@ -337,7 +337,9 @@ __device__ __forceinline__ void bwd_quadrant(const BatchArgs& a, const ReqDev& q
 // item 0.455 ms.
 template <int C>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) k_render_bwd(BatchArgs a) {
-  if (a.dev->overflow) return;
+  // both reads in flight before the first branch: most workgroups of a
+  // serving slot's launch lie past the batch's tiles and leave here
+  const int overflow = a.dev->overflow;
   const BatchHdr h = batch_hdr(a);
   __shared__ __align__(16) float FE[GROUP * C];
   __shared__ double2 RXY[GROUP];
@@ -348,7 +350,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
   const int n_items = 4 * h.n_tiles;
   const int b = (int)blockIdx.x;
   const int item = 4 * (8 * (b >> 5) + (b & 7)) + ((b >> 3) & 3);
-  if (item >= n_items) return;
+  if (overflow != 0 || item >= n_items) return;
   const int t = a.tile_order[item >> 2];
   const int r = req_of_tile(a, h, t);
   if (r < 0) return;

@@ -304,9 +304,12 @@ __device__ __forceinline__ void render_quadrant(const BatchArgs& a, const ReqDev
 // statistics.
 template <int C, bool COUNT, bool TABLE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_render(BatchArgs a) {
-  if (a.dev->overflow) return;
   if (!TABLE) a.table = nullptr;
+  // both reads in flight before the first branch: most workgroups of a
+  // serving slot's launch lie past the batch's tiles and leave here
+  const int overflow = a.dev->overflow;
   const BatchHdr h = batch_hdr(a);
+  if (overflow != 0 || (int)blockIdx.x >= h.n_tiles) return;
   constexpr int B = wave_batch<C>();
   __shared__ WaveLDS<C, B> LW[4];
   const int lane = threadIdx.x & 63;
